@@ -1,0 +1,76 @@
+/*
+ * fmmds oracle: TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU build of the FMM data structures of
+ * Hu, Gumerov and Duraiswami, "Parallel Algorithms for Constructing Data
+ * Structures for Fast Multipole Methods" (arXiv 1301.1704). It exists so the
+ * GPU library can be checked against it; only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it. It shares no code,
+ * header or constant with the GPU library.
+ *
+ * All pointers are host pointers. Coordinates are FP32 xyz triples (array of
+ * structs) in the half-open unit cube [0, 1)^3 (Section 2.4 assumes the
+ * points are already scaled into the unit cube).
+ *
+ * Set index: 0 = sources, 1 = receivers. List kind: 2 = E2 (neighbor list,
+ * Section 2.4 item 2 and Section 3.2), 4 = E4 (M2L interaction list,
+ * Section 2.4 item 4).
+ */
+#ifndef FMMDS_ORACLE_H
+#define FMMDS_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OREF_OK = 0,
+  OREF_ERR_ARG = 1,      /* NULL pointer, n == 0, n >= 2^32-1, bad key_bits or max_level */
+  OREF_ERR_RANGE = 2,    /* a coordinate is NaN, infinite or outside [0, 1) */
+  OREF_ERR_NOMEM = 3,    /* host allocation failed */
+  OREF_ERR_LEVEL = 5,    /* list or table query outside the built levels */
+  OREF_ERR_OVERFLOW = 6  /* a list at one level has 2^32 or more entries */
+};
+
+typedef struct oref_tree oref_tree;
+
+/* Morton keys of n points at level L (key of box containing each point).
+ * Returns OREF_ERR_RANGE if any coordinate is outside [0, 1). */
+int oref_point_keys(const float* xyz, uint32_t n, uint32_t level, uint64_t* keys_out);
+
+/* Build the tables (and, if with_lists != 0, E2/E4 lists for levels 2..depth).
+ * recv == NULL: receivers are the sources (n_recv ignored). */
+int oref_build(const float* src, uint32_t n_src, const float* recv, uint32_t n_recv,
+               uint32_t key_bits, uint32_t cluster_s, uint32_t max_level, int with_lists,
+               oref_tree** out);
+void oref_free(oref_tree* t);
+
+uint32_t oref_depth(const oref_tree* t);
+uint32_t oref_n_points(const oref_tree* t, int set);
+uint32_t oref_n_boxes(const oref_tree* t, int set, uint32_t level);
+/* Max points in one box of the level (used by the depth rule). */
+uint32_t oref_max_occupancy(const oref_tree* t, int set, uint32_t level);
+
+int oref_perm(const oref_tree* t, int set, uint32_t* out);                 /* n */
+int oref_sorted_xyz(const oref_tree* t, int set, float* out);              /* 3n */
+int oref_keys(const oref_tree* t, int set, uint32_t level, uint64_t* out); /* n_l */
+int oref_begin(const oref_tree* t, int set, uint32_t level, uint32_t* out);/* n_l + 1 */
+int oref_parent(const oref_tree* t, int set, uint32_t level, uint32_t* out);/* n_l, level >= 1 */
+int oref_child(const oref_tree* t, int set, uint32_t level, uint32_t* out); /* n_l + 1, level < depth */
+
+/* Whole lists (built with with_lists != 0). */
+int oref_list_sizes(const oref_tree* t, int kind, uint32_t level, uint32_t* n_recv_boxes,
+                    uint64_t* n_entries);
+int oref_list(const oref_tree* t, int kind, uint32_t level, uint32_t* offsets, uint32_t* entries);
+
+/* One receiver box's list, computed on demand from the definition; entries
+ * must hold 189. Returns the entry count, or minus a status code. */
+int oref_box_list(const oref_tree* t, int kind, uint32_t level, uint32_t recv_box,
+                  uint32_t* entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

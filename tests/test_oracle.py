@@ -1,0 +1,281 @@
+"""Pins for the CPU oracle, against what the paper and the mathematics fix.
+
+None of these tests re-runs the oracle's own formulas: expected values come
+from exact rational arithmetic and pair enumeration (tests/brute.py), closed
+forms on the full grid, a hand-worked example, and invariants that any correct
+build satisfies (arXiv 1301.1704, Section 2.4 and Section 3).
+"""
+import numpy as np
+import pytest
+
+import brute
+import golden_io
+from paper_1301_1704_amd import inputs as I
+
+pytestmark = pytest.mark.timeout(300) if hasattr(pytest.mark, "timeout") else []
+
+
+def _tiny_sets():
+    """(name, src, recv or None, max_level) cases of a few hundred points."""
+    rng_u = I.uniform_points(11, 300)
+    cl = I.cluster_points(12, 240, I.cluster_centres(13, 4), 0.03)
+    # points on box faces of level 3 and their FP32 neighbours
+    faces = []
+    for k in (0, 1, 3, 4, 7):
+        v = np.float32(k / 8.0)
+        for w in (v, np.nextafter(v, np.float32(1)), np.nextafter(v, np.float32(0))):
+            if 0 <= w < 1:
+                faces.append(w)
+    faces = np.asarray(faces, dtype=np.float32)
+    fpts = np.stack(np.meshgrid(faces, faces[::2], faces[1::3], indexing="ij"), -1).reshape(-1, 3)
+    dup = np.concatenate([rng_u[:40], rng_u[:40], rng_u[10:30]], axis=0)
+    return [
+        ("uniform-shared-L3", rng_u, None, 3),
+        ("uniform-separate-L4", rng_u[:150], I.uniform_points(14, 170), 4),
+        ("clusters-separate-L4", cl, rng_u[:90], 4),
+        ("faces-shared-L3", np.ascontiguousarray(fpts, dtype=np.float32), None, 3),
+        ("duplicates-separate-L3", dup, cl[:60], 3),
+        ("single-point-L2", rng_u[:1], rng_u[5:6], 2),
+    ]
+
+
+CASES = _tiny_sets()
+
+
+# ----------------------------------------------------------------- keys
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 10, 13, 21])
+def test_keys_match_exact_digits(oracle_lib, L):
+    """Quantization and interleave: every 3-bit digit of the key is the
+    octant of the point's box inside its parent, with box coordinates from
+    exact rational arithmetic at each level."""
+    pts = [I.uniform_points(21, 40)]
+    # box faces at this level and their FP32 neighbours
+    f = []
+    for k in (0, 1, (1 << L) - 1, 1 << (L - 1), 3):
+        v = np.float32(min(k, (1 << L) - 1) / float(1 << L))
+        f += [v, np.nextafter(v, np.float32(1)), np.nextafter(v, np.float32(0))]
+    f = np.asarray([w for w in f if 0 <= w < 1], dtype=np.float32)
+    pts.append(np.stack([f, f[::-1], np.roll(f, 1)], axis=1))
+    pts.append(np.asarray([[0.0, -0.0, 1e-40], [np.float32(1 - 2 ** -24)] * 3], dtype=np.float32))
+    p = np.concatenate(pts, axis=0).astype(np.float32)
+    keys = oracle_lib.point_keys(p, L)
+    for i in range(p.shape[0]):
+        assert int(keys[i]) == brute.morton_by_digits(p[i], L), (L, p[i])
+
+
+def test_key_bit_convention(oracle_lib):
+    """The library's bit order reading: x to bit 0, y to bit 1, z to bit 2
+    of each 3-bit digit (the paper fixes none; parity unpinned by the
+    paper, pinned here as the stated convention)."""
+    q = np.float32(0.5)
+    p = np.asarray([[q, 0, 0], [0, q, 0], [0, 0, q]], dtype=np.float32)
+    assert oracle_lib.point_keys(p, 1).tolist() == [1, 2, 4]
+    assert oracle_lib.point_keys(p, 2).tolist() == [8, 16, 32]
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf, 1.0, 1.5, -1e-30, -0.5])
+def test_range_errors(oracle_lib, bad):
+    p = np.asarray([[0.25, 0.25, 0.25], [0.5, bad, 0.5]], dtype=np.float32)
+    with pytest.raises(oracle_lib.OracleError) as e:
+        oracle_lib.point_keys(p, 4)
+    assert e.value.status == oracle_lib.ERR_RANGE
+    with pytest.raises(oracle_lib.OracleError) as e:
+        oracle_lib.OracleTree(p, key_bits=64, max_level=4)
+    assert e.value.status == oracle_lib.ERR_RANGE
+
+
+def test_negative_zero_and_subnormal_accepted(oracle_lib):
+    p = np.asarray([[-0.0, 1e-45, 1e-38]], dtype=np.float32)
+    assert oracle_lib.point_keys(p, 10).tolist() == [0]
+
+
+@pytest.mark.parametrize("kb,L,ok", [(32, 10, True), (32, 11, False), (64, 21, True),
+                                     (64, 22, False), (64, 1, False), (16, 4, False)])
+def test_argument_checks(oracle_lib, kb, L, ok):
+    p = I.uniform_points(3, 10)
+    if ok:
+        t = oracle_lib.OracleTree(p, key_bits=kb, max_level=L, with_lists=False)
+        assert t.depth == L
+    else:
+        with pytest.raises(oracle_lib.OracleError) as e:
+            oracle_lib.OracleTree(p, key_bits=kb, max_level=L)
+        assert e.value.status == oracle_lib.ERR_ARG
+
+
+# ----------------------------------------------------------- hand example
+
+def test_worked_example(oracle_lib):
+    g = golden_io.read_kv("worked_example_level2.txt")
+    t = oracle_lib.OracleTree(np.asarray(g["src"], np.float32), np.asarray(g["recv"], np.float32),
+                              key_bits=32, max_level=g["max_level"])
+    assert t.depth == 2
+    for s, name in ((0, "src"), (1, "recv")):
+        assert t.perm(s).tolist() == g[f"{name}_perm"]
+        for l in range(3):
+            assert t.keys(s, l).tolist() == g[f"{name}_keys_{l}"]
+            assert t.begin(s, l).tolist() == g[f"{name}_begin_{l}"]
+            if l >= 1:
+                assert t.parent(s, l).tolist() == g[f"{name}_parent_{l}"]
+            if l < 2:
+                assert t.child(s, l).tolist() == g[f"{name}_child_{l}"]
+    for kind in (2, 4):
+        off, ent = t.list(kind, 2)
+        assert off.tolist() == g[f"e{kind}_offsets_2"]
+        assert ent.tolist() == g[f"e{kind}_entries_2"]
+
+
+# ------------------------------------------------------------ brute force
+
+@pytest.mark.parametrize("name,src,recv,L", CASES, ids=[c[0] for c in CASES])
+def test_tables_and_order_by_brute_force(oracle_lib, name, src, recv, L):
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
+    for s, pts in ((0, src), (1, src if recv is None else recv)):
+        perm, tab = brute.tables([tuple(p) for p in pts], L, L)
+        assert t.perm(s).tolist() == perm
+        assert t.sorted_xyz(s).tobytes() == np.ascontiguousarray(pts[perm]).tobytes()
+        for l in range(L + 1):
+            assert t.keys(s, l).tolist() == tab[l]["keys"], (s, l)
+            assert t.begin(s, l).tolist() == tab[l]["begin"], (s, l)
+            if l >= 1:
+                assert t.parent(s, l).tolist() == tab[l]["parent"], (s, l)
+            if l < L:
+                assert t.child(s, l).tolist() == tab[l]["child"], (s, l)
+
+
+@pytest.mark.parametrize("name,src,recv,L", CASES, ids=[c[0] for c in CASES])
+def test_lists_by_pair_enumeration(oracle_lib, name, src, recv, L):
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
+    sp = [tuple(p) for p in src]
+    rp = sp if recv is None else [tuple(p) for p in recv]
+    exp = brute.lists_by_pairs(sp, rp, L, L)
+    for l in range(2, L + 1):
+        for kind, lists in ((2, exp[l][0]), (4, exp[l][1])):
+            off, ent = t.list(kind, l)
+            eo, ee = brute.csr(lists)
+            assert off.tolist() == eo.tolist(), (kind, l)
+            assert ent.tolist() == ee.tolist(), (kind, l)
+            for r in range(len(lists)):
+                assert t.box_list(kind, l, r).tolist() == lists[r]
+
+
+@pytest.mark.parametrize("s", [1, 3, 8, 40, 1000])
+def test_depth_rule_by_brute_force(oracle_lib, s):
+    src = I.cluster_points(31, 300, I.cluster_centres(32, 3), 0.02)
+    recv = I.uniform_points(33, 200)
+    L = 5
+    exp = L
+    for l in range(2, L + 1):
+        if (brute.max_occupancy([tuple(p) for p in src], l) <= s and
+                brute.max_occupancy([tuple(p) for p in recv], l) <= s):
+            exp = l
+            break
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, cluster_s=s, max_level=L)
+    assert t.depth == exp
+    for l in range(2, exp + 1):
+        assert t.max_occupancy(0, l) == brute.max_occupancy([tuple(p) for p in src], l)
+    with pytest.raises(oracle_lib.OracleError):
+        t.child(0, exp)  # the finest kept level has no children
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("row", golden_io.read_table("closed_forms.txt")[:5])
+def test_full_grid_closed_forms(oracle_lib, row):
+    L, e2_total, e4_total = row
+    t = oracle_lib.OracleTree(I.full_grid_points(L), key_bits=64, max_level=L)
+    assert t.n_boxes(0, L) == 8 ** L
+    for l in range(L + 1):
+        b = t.begin(0, l)
+        assert np.all(np.diff(b.astype(np.int64)) == 8 ** (L - l))
+    o2, _ = t.list(2, L)
+    o4, _ = t.list(4, L)
+    assert int(o2[-1]) == e2_total and int(o4[-1]) == e4_total
+    # per box: |E2| = prod b, |E4| = prod a - prod b
+    m = 1 << L
+    c = np.arange(m)
+    bx = 3 - (c == 0) - (c == m - 1)
+    p = c >> 1
+    ax = 2 * (3 - (p == 0) - (p == (m >> 1) - 1))
+    keys = t.keys(0, L)
+    co = np.zeros((keys.size, 3), dtype=np.int64)
+    for bit in range(L):
+        for d in range(3):
+            co[:, d] |= ((keys >> np.uint64(3 * bit + d)) & np.uint64(1)).astype(np.int64) << bit
+    B = bx[co[:, 0]] * bx[co[:, 1]] * bx[co[:, 2]]
+    A = ax[co[:, 0]] * ax[co[:, 1]] * ax[co[:, 2]]
+    assert np.array_equal(np.diff(o2.astype(np.int64)), B)
+    assert np.array_equal(np.diff(o4.astype(np.int64)), A - B)
+    if L >= 3:
+        assert B.max() == 27 and (A - B).max() == 189
+
+
+# -------------------------------------------------------------- invariants
+
+def _inv_cases():
+    return [
+        ("uniform", I.uniform_points(41, 3000), I.uniform_points(42, 2500), 5),
+        ("sphere+clusters", I.sphere_cluster_points(43, 44, 4000),
+         I.sphere_cluster_points(45, 44, 3000), 6),
+    ]
+
+
+@pytest.mark.parametrize("name,src,recv,L", _inv_cases(), ids=[c[0] for c in _inv_cases()])
+def test_partition_of_sources(oracle_lib, name, src, recv, L):
+    """For every receiver leaf b, the near list E2(b) at the finest level and
+    the interaction lists E4 of b's ancestors at levels 2..D cover every
+    source point exactly once (the near/far split of Eq. (2) done
+    hierarchically, Section 2.4)."""
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
+    D = t.depth
+    N = src.shape[0]
+    sb = {l: t.begin(0, l).astype(np.int64) for l in range(D + 1)}
+    lists = {(k, l): t.list(k, l) for k in (2, 4) for l in range(2, D + 1)}
+    rpar = {l: t.parent(1, l) for l in range(1, D + 1)}
+    # first sorted source point of each source box, and the leaf range it spans
+    n_leaf = t.n_boxes(1, D)
+    for b in range(n_leaf):
+        covered = np.zeros(N, dtype=np.int32)
+        anc = b
+        for l in range(D, 1, -1):
+            kinds = (2, 4) if l == D else (4,)
+            for k in kinds:
+                off, ent = lists[(k, l)]
+                for s in ent[off[anc]:off[anc + 1]]:
+                    covered[sb[l][s]:sb[l][s + 1]] += 1
+            anc = int(rpar[l][anc])
+        assert covered.min() == 1 and covered.max() == 1, b
+        if b > 60:
+            break
+
+
+def test_invariants_and_symmetry_shared(oracle_lib):
+    p = I.sphere_cluster_points(51, 52, 5000)
+    t = oracle_lib.OracleTree(p, key_bits=64, max_level=6)
+    n = p.shape[0]
+    perm = t.perm(0)
+    assert np.array_equal(np.sort(perm), np.arange(n, dtype=np.uint32))
+    keys6 = oracle_lib.point_keys(p, 6)[perm]
+    assert np.all(np.diff(keys6.astype(np.int64)) >= 0)
+    ties = np.diff(keys6.astype(np.int64)) == 0
+    assert np.all(np.diff(perm.astype(np.int64))[ties] > 0)
+    for l in range(7):
+        k = t.keys(0, l)
+        b = t.begin(0, l)
+        assert np.all(np.diff(k.astype(np.int64)) > 0)
+        assert b[0] == 0 and b[-1] == n and np.all(np.diff(b.astype(np.int64)) > 0)
+        if l < 6:
+            c = t.child(0, l)
+            assert c[0] == 0 and c[-1] == t.n_boxes(0, l + 1)
+            par = t.parent(0, l + 1)
+            assert np.array_equal(np.repeat(np.arange(k.size), np.diff(c.astype(np.int64))), par)
+    for l in range(2, 7):
+        for kind in (2, 4):
+            off, ent = t.list(kind, l)
+            pairs = set()
+            for r in range(off.size - 1):
+                row = ent[off[r]:off[r + 1]]
+                assert np.all(np.diff(row.astype(np.int64)) > 0)
+                pairs.update((r, int(s)) for s in row)
+            assert pairs == {(s, r) for (r, s) in pairs}, (kind, l)
+            assert np.diff(off.astype(np.int64)).max() <= (27 if kind == 2 else 189)
