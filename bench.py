@@ -1,0 +1,165 @@
+"""Benchmark: points/sec of the full FMM data-structure build on one MI355X.
+
+One step = one fmmds_build (keys, sort, permutation, tables of every level,
+E2 and E4 lists of levels 2..depth, for both point sets) from inputs already
+resident in HBM, followed by fmmds_free. Default workload: two independent
+uniform sets of 2^24 points, max level 8, 64-bit keys.
+
+Prints ONE JSON line on stdout; progress and the per-kernel breakdown go to
+stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/sec full FMM data-structure build at N=M=2^24; batched builds/sec vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from paper_1301_1704_amd import inputs as I
+    if name == "uniform":
+        return I.config_plain_uniform()
+    if name == "nonuniform":
+        return I.config_plain_nonuniform()
+    if name == "small":
+        return I.config_plain_small()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(name: str):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    1/8 of the points with one level less, i.e. the same points per box and
+    the same list lengths, on 1/8 of the boxes."""
+    import oracle
+    from paper_1301_1704_amd import inputs as I
+    if name == "uniform":
+        n, L = 1 << 21, 7
+        src, recv, kb, s = I.uniform_points(2, n), I.uniform_points(3, n), 64, 0
+        desc = "2^21 + 2^21 uniform points, max level 7 (same density as 2^24 at level 8)"
+    elif name == "nonuniform":
+        n, L = 1 << 21, 9
+        src = I.sphere_cluster_points(5, 4, n)
+        recv = I.sphere_cluster_points(6, 4, n)
+        kb, s = 64, 64
+        desc = "2^21 + 2^21 sphere+cluster points, max level 9, s=64"
+    else:
+        c = I.config_plain_small()
+        src, recv, kb, s, L = c["src"], None, 32, 0, 5
+        n = src.shape[0]
+        desc = "the full 65,536-point workload"
+    oracle.lib()
+    t0 = time.perf_counter()
+    t = oracle.OracleTree(src, recv, key_bits=kb, cluster_s=s, max_level=L, with_lists=True)
+    dt = time.perf_counter() - t0
+    t.close()
+    pts = n if recv is None else 2 * n
+    return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": desc, "seconds": round(dt, 3),
+            "cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "nonuniform", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the per-kernel event timing (no roofline object)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent point sets shard trivially, one set spans one GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+    import paper_1301_1704_amd as F
+
+    if not os.path.exists(F.LIB_PATH):
+        from paper_1301_1704_amd import build as hb
+        hb.build()
+    c = workload(args.workload)
+    log(f"workload {c['name']}: generating inputs")
+    src = torch.from_numpy(c["src"]).cuda()
+    recv = None if c["recv"] is None else torch.from_numpy(c["recv"]).cuda()
+    n_pts = src.shape[0] + (0 if recv is None else recv.shape[0])
+    kw = dict(max_level=c["max_level"], key_bits=c["key_bits"], cluster_s=c["cluster_s"])
+
+    t = F.build(src, recv, **kw)
+    torch.cuda.synchronize()
+    info = {"depth": t.depth,
+            "src_boxes_finest": t.n_boxes(0, t.depth),
+            "recv_boxes_finest": t.n_boxes(1, t.depth),
+            "e2_entries": int(sum(t.neighbors(l)[3] for l in range(2, t.depth + 1))),
+            "e4_entries": int(sum(t.interactions(l)[3] for l in range(2, t.depth + 1)))}
+    t.free()
+    for _ in range(args.warmup):
+        F.build(src, recv, **kw).free()
+    torch.cuda.synchronize()
+
+    profile = not args.no_profile
+    if profile:
+        F.profile_reset()
+        F.profile_enable(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F.build(src, recv, **kw).free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    if profile:
+        F.profile_enable(False)
+        stats = F.profile_read()
+    value = n_pts / dt
+
+    line = {"metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": c["name"], "n_src": int(src.shape[0]),
+                       "n_recv": int(src.shape[0] if recv is None else recv.shape[0]),
+                       "max_level": c["max_level"], "key_bits": c["key_bits"],
+                       "cluster_s": c["cluster_s"], **info}}
+    if profile and stats:
+        total = sum(v["total_ms"] for v in stats.values())
+        log(f"{'kernel':16s} {'launches':>8s} {'avg_us':>10s} {'share':>6s} {'GB/s':>8s}")
+        for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_ms"]):
+            log(f"{k:16s} {v['launches']:8d} {1e3 * v['total_ms'] / v['launches']:10.1f} "
+                f"{v['total_ms'] / total:6.1%} {v['bytes'] / (v['total_ms'] * 1e6):8.1f}")
+        dom, v = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
+        per_launch = v["bytes"] / v["launches"]
+        avg_ms = v["total_ms"] / v["launches"]
+        achieved = per_launch / (avg_ms * 1e6)
+        line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": dom, "avg_launch_us": avg_ms * 1e3,
+                            "bytes_per_launch": per_launch,
+                            "kernel_time_share": v["total_ms"] / total}
+        line["kernels"] = {k: {"launches": s["launches"],
+                               "avg_us": round(1e3 * s["total_ms"] / s["launches"], 2),
+                               "GBps": round(s["bytes"] / (s["total_ms"] * 1e6), 1)}
+                           for k, s in stats.items()}
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a sample")
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

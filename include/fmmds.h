@@ -1,0 +1,178 @@
+/*
+ * fmmds: FMM data-structure construction on AMD Instinct MI355X (gfx950).
+ *
+ * Builds, on one GPU, the data structures of a multilevel fast multipole
+ * method for N source points and M receiver points in the unit cube, as
+ * defined by Hu, Gumerov and Duraiswami, "Parallel Algorithms for
+ * Constructing Data Structures for Fast Multipole Methods" (arXiv 1301.1704):
+ *
+ *   - the Morton index of every point's box at the finest level and the
+ *     points reordered by it (Section 3.1, Algorithm 1);
+ *   - per level, the Morton indices of the nonempty boxes and their bookmarks,
+ *     i.e. the first reordered point of each box (Section 3.2, Algorithm 3);
+ *   - per level, parent and children links (the parent/children queries of
+ *     Section 3.4; the parent index is the child index shifted right by one
+ *     level, Section 4.2);
+ *   - per level 2..depth, for every nonempty receiver box, the E2 neighbor
+ *     list (at most 27 nonempty source boxes, Section 2.4 item 2 and
+ *     Algorithm 4) and the E4 interaction (M2L) list (at most 189 nonempty
+ *     source boxes, Section 2.4 item 4).
+ *
+ * Conventions (the paper leaves these open):
+ *   - level l has 8^l boxes; a box has integer coordinates (cx, cy, cz) in
+ *     [0, 2^l)^3 and Morton index with bit b of cx, cy, cz at bit 3b, 3b+1,
+ *     3b+2. A point x is in the box floor(x * 2^l) per axis, computed in FP32
+ *     (scaling by 2^l is exact). There is no level marker bit.
+ *   - points are ordered by (finest-level Morton index, original index), so
+ *     the order is deterministic.
+ *   - E2 of a box includes the box itself; the domain is not periodic.
+ *   - E4(r) = nonempty source boxes s with max_d |c_s - c_r| >= 2 whose
+ *     parent is within max_d |p_s - p_r| <= 1 of r's parent.
+ *   - list entries are ranks of nonempty source boxes at the same level (the
+ *     index into that level's source tables), in ascending order.
+ *   - depth: if cluster_s == 0 the depth is max_level. Otherwise it is the
+ *     smallest level l in [2, max_level] at which no source box and no
+ *     receiver box holds more than cluster_s points (Section 3.1: the cluster
+ *     size fixes the finest level), or max_level if no level qualifies.
+ *
+ * Memory: every pointer passed in or returned is a DEVICE pointer on the
+ * current HIP device unless stated otherwise. The caller owns the inputs; the
+ * library owns every output until fmmds_free. Errors never throw; on error
+ * *out is set to NULL and nothing leaks.
+ *
+ * Threading: distinct trees are independent; a tree is read-only after
+ * fmmds_build returns, so concurrent reads are safe.
+ */
+#ifndef FMMDS_H
+#define FMMDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMMDS_MAX_LEVEL 21 /* 3 * 21 = 63 key bits */
+
+typedef enum fmmds_status {
+  FMMDS_OK = 0,
+  FMMDS_ERR_ARG = 1,      /* NULL pointer, n == 0, n >= 2^32 - 1, key_bits not 32/64,
+                             max_level outside [2, key_bits / 3] */
+  FMMDS_ERR_RANGE = 2,    /* a coordinate is NaN, infinite or outside [0, 1) (-0.0 is accepted) */
+  FMMDS_ERR_NOMEM = 3,    /* device (or callback) allocation failed */
+  FMMDS_ERR_DEVICE = 4,   /* a HIP runtime call failed */
+  FMMDS_ERR_LEVEL = 5,    /* list query outside [2, depth] */
+  FMMDS_ERR_OVERFLOW = 6  /* a list at one level would hold 2^32 or more entries */
+} fmmds_status;
+
+/* Optional allocator: return `bytes` of device memory usable on `stream`
+ * (a hipStream_t), or NULL on failure. `release` gets back exactly the
+ * pointers `alloc` returned, with the same byte counts. */
+typedef void* (*fmmds_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*fmmds_release_fn)(void* ctx, void* ptr, size_t bytes, void* stream);
+
+typedef struct fmmds_options {
+  uint32_t key_bits;   /* 32 or 64: width of the per-level key arrays */
+  uint32_t cluster_s;  /* 0: depth = max_level; else the cluster-size rule above */
+  uint32_t max_level;  /* finest level considered, in [2, key_bits / 3] */
+  uint32_t reserved;   /* must be 0 */
+  void* stream;        /* hipStream_t the build is ordered on; NULL = null stream */
+  fmmds_alloc_fn alloc;      /* NULL: stream-ordered hipMallocAsync pool */
+  fmmds_release_fn release;  /* must be set iff alloc is set */
+  void* alloc_ctx;
+} fmmds_options;
+
+/* One level of one point set. */
+typedef struct fmmds_level {
+  uint32_t n;              /* number of nonempty boxes */
+  const void* key;         /* n Morton indices, ascending; uint32_t* if key_bits == 32,
+                              else uint64_t* */
+  const uint32_t* begin;   /* n + 1: first reordered point of each box; begin[n] = points */
+  const uint32_t* parent;  /* n: rank of the parent at level - 1; NULL at level 0 */
+  const uint32_t* child;   /* n + 1: first child rank at level + 1, child[n] = boxes at
+                              level + 1; NULL at level == depth */
+} fmmds_level;
+
+typedef struct fmmds_tree {
+  uint32_t depth;          /* finest level built (lists exist for 2..depth) */
+  uint32_t key_bits;
+  uint32_t max_level;
+  uint32_t shared;         /* 1: receivers are the sources; recv fields alias src */
+  uint32_t n_src, n_recv;
+  const uint32_t* src_perm;       /* n_src: original index of each reordered source */
+  const uint32_t* recv_perm;      /* n_recv */
+  const float* src_sorted_xyz;    /* 3 * n_src: src_xyz[perm[k]], bit copies */
+  const float* recv_sorted_xyz;   /* 3 * n_recv */
+  fmmds_level src[FMMDS_MAX_LEVEL + 1];   /* levels 0..depth are valid */
+  fmmds_level recv[FMMDS_MAX_LEVEL + 1];
+  void* impl;                     /* private */
+} fmmds_tree;
+
+/*
+ * Build all tables and lists (Algorithm 5 of the paper, with the lists of
+ * Section 3.2 at every level 2..depth).
+ *   src_xyz:  device, 3 * n_src FP32 values, (x, y, z) per point.
+ *   recv_xyz: device, 3 * n_recv FP32 values, or NULL: receivers are the
+ *             sources and n_recv is ignored.
+ *   opt:      host, required.
+ *   out:      host; receives a tree owned by the library.
+ * Synchronous: when it returns FMMDS_OK every output is complete and visible
+ * to work later enqueued on opt->stream. Inputs are not retained.
+ */
+fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
+                         uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
+
+/*
+ * E2 neighbor list of every nonempty receiver box at `level` in [2, depth]
+ * (Section 3.2, NeighborBookmark / NeighborList), as CSR:
+ *   *offsets: device, *n_recv_boxes + 1 entries; box j's list is
+ *             entries[offsets[j] .. offsets[j+1]).
+ *   *entries: device, *n_entries source ranks at `level`, ascending per box.
+ * The arrays belong to the tree. FMMDS_ERR_LEVEL outside [2, depth].
+ */
+fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
+                             const uint32_t** entries, uint32_t* n_recv_boxes,
+                             uint64_t* n_entries);
+
+/*
+ * E4 interaction (M2L) list of every nonempty receiver box at `level` in
+ * [2, depth] (Section 2.4 item 4), same CSR layout as fmmds_neighbors.
+ */
+fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
+                                const uint32_t** entries, uint32_t* n_recv_boxes,
+                                uint64_t* n_entries);
+
+/* Release every output of the tree (ordered on the build's stream). NULL is
+ * accepted. Pointers obtained from the tree become invalid. */
+void fmmds_free(fmmds_tree* t);
+
+/*
+ * Diagnostics: per-kernel timing. While enabled, every kernel a build
+ * launches is bracketed by HIP events on the build stream; at the end of each
+ * build the durations are added, per kernel, to process-wide totals together
+ * with the algorithmic bytes of each launch (the reads and writes the method
+ * itself needs, independent of caching). Enabling adds one stream
+ * synchronization at the end of each build. Not thread-safe against
+ * concurrent builds.
+ */
+typedef struct fmmds_kernel_stat {
+  char name[32];     /* kernel name, e.g. "sort_pass", "list_fill" */
+  uint64_t launches;
+  double total_ms;   /* summed event-measured durations */
+  double bytes;      /* summed algorithmic bytes */
+} fmmds_kernel_stat;
+
+void fmmds_profile_enable(int on);
+void fmmds_profile_reset(void);
+/* Copies up to `cap` entries into `out` (host); returns the number of kernels
+ * with statistics. */
+uint32_t fmmds_profile_read(fmmds_kernel_stat* out, uint32_t cap);
+
+/* Human-readable name of a status code (static string). */
+const char* fmmds_status_string(fmmds_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMMDS_H */

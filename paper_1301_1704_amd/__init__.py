@@ -1,0 +1,300 @@
+"""Python binding of libfmmds (include/fmmds.h): argument marshalling only.
+
+Every step of the build runs in the library's HIP kernels on the GPU. This
+module passes device pointers of torch tensors and torch's current stream to
+the C ABI, and copies results back when asked. There is no CPU path: if the
+library is missing or no GPU is present the calls raise.
+
+The HIP runtime: torch ships its own libamdhip64.so.7. torch is imported
+before libfmmds.so is loaded, so the library binds to that same runtime
+instance (one HIP runtime per process) and can use torch's memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmmds.so")
+MAX_LEVEL = 21
+
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_LEVEL, ERR_OVERFLOW = 0, 1, 2, 3, 4, 5, 6
+SRC, RECV = 0, 1
+
+_u32, _u64, _vp = C.c_uint32, C.c_uint64, C.c_void_p
+ALLOC_FN = C.CFUNCTYPE(_vp, _vp, C.c_size_t, _vp)
+RELEASE_FN = C.CFUNCTYPE(None, _vp, _vp, C.c_size_t, _vp)
+
+
+class Options(C.Structure):
+    _fields_ = [("key_bits", _u32), ("cluster_s", _u32), ("max_level", _u32),
+                ("reserved", _u32), ("stream", _vp), ("alloc", ALLOC_FN),
+                ("release", RELEASE_FN), ("alloc_ctx", _vp)]
+
+
+class Level(C.Structure):
+    _fields_ = [("n", _u32), ("key", _vp), ("begin", _vp), ("parent", _vp), ("child", _vp)]
+
+
+class TreeStruct(C.Structure):
+    _fields_ = [("depth", _u32), ("key_bits", _u32), ("max_level", _u32), ("shared", _u32),
+                ("n_src", _u32), ("n_recv", _u32),
+                ("src_perm", _vp), ("recv_perm", _vp),
+                ("src_sorted_xyz", _vp), ("recv_sorted_xyz", _vp),
+                ("src", Level * (MAX_LEVEL + 1)), ("recv", Level * (MAX_LEVEL + 1)),
+                ("impl", _vp)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", _u64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
+class FmmdsError(RuntimeError):
+    def __init__(self, status: int, what: str = "fmmds"):
+        name = _lib().fmmds_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{what}: {name} (status {status})")
+        self.status = status
+
+
+_LIB = None
+_HIP = None
+
+
+def _lib():
+    global _LIB, _HIP
+    if _LIB is None:
+        import torch  # binds the HIP runtime first (see module docstring)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1301_1704_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.fmmds_build.argtypes = [_vp, _u32, _vp, _u32, C.POINTER(Options),
+                                  C.POINTER(C.POINTER(TreeStruct))]
+        L.fmmds_build.restype = C.c_int
+        for f in ("fmmds_neighbors", "fmmds_interactions"):
+            getattr(L, f).argtypes = [C.POINTER(TreeStruct), _u32, C.POINTER(_vp), C.POINTER(_vp),
+                                      C.POINTER(_u32), C.POINTER(_u64)]
+            getattr(L, f).restype = C.c_int
+        L.fmmds_free.argtypes = [C.POINTER(TreeStruct)]
+        L.fmmds_free.restype = None
+        L.fmmds_profile_enable.argtypes = [C.c_int]
+        L.fmmds_profile_enable.restype = None
+        L.fmmds_profile_reset.restype = None
+        L.fmmds_profile_read.argtypes = [C.POINTER(KernelStat), _u32]
+        L.fmmds_profile_read.restype = _u32
+        L.fmmds_status_string.argtypes = [C.c_int]
+        L.fmmds_status_string.restype = C.c_char_p
+        H = C.CDLL("libamdhip64.so.7")  # the instance torch already loaded
+        H.hipMemcpy.argtypes = [_vp, _vp, C.c_size_t, C.c_int]
+        H.hipMemcpy.restype = C.c_int
+        H.hipDeviceSynchronize.restype = C.c_int
+        _LIB, _HIP = L, H
+        del torch
+    return _LIB
+
+
+def exported_symbols():
+    return ["fmmds_build", "fmmds_neighbors", "fmmds_interactions", "fmmds_free",
+            "fmmds_profile_enable", "fmmds_profile_reset", "fmmds_profile_read",
+            "fmmds_status_string"]
+
+
+def profile_enable(on: bool = True):
+    """Time every kernel of later builds with HIP events on the build stream."""
+    _lib().fmmds_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib().fmmds_profile_reset()
+
+
+def profile_read() -> dict:
+    """{kernel: {"launches", "total_ms", "bytes"}} accumulated since the reset."""
+    buf = (KernelStat * 32)()
+    n = _lib().fmmds_profile_read(buf, 32)
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches),
+                                   "total_ms": float(buf[i].total_ms),
+                                   "bytes": float(buf[i].bytes)} for i in range(min(n, 32))}
+
+
+def _device_to_host(ptr: int, count: int, dtype) -> np.ndarray:
+    out = np.empty(count, dtype=dtype)
+    if count:
+        st = _HIP.hipMemcpy(out.ctypes.data_as(_vp), _vp(ptr), out.nbytes, 2)
+        if st != 0:
+            raise FmmdsError(ERR_DEVICE, f"hipMemcpy (hip error {st})")
+    return out
+
+
+class _TorchAllocator:
+    """Routes the library's allocations through torch's caching allocator."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.alloc = ALLOC_FN(self._alloc)
+        self.release = RELEASE_FN(self._release)
+
+    def _alloc(self, ctx, nbytes, stream):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or 0)
+        except Exception:
+            return None
+
+    def _release(self, ctx, ptr, nbytes, stream):
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+
+_TORCH_ALLOC = None
+
+
+class Tree:
+    """A built tree: device tables and lists owned by libfmmds."""
+
+    def __init__(self, handle, allocator=None):
+        self._h = handle
+        self._alloc = allocator  # keeps callbacks alive as long as the tree
+        t = handle.contents
+        self.depth = int(t.depth)
+        self.key_bits = int(t.key_bits)
+        self.max_level = int(t.max_level)
+        self.shared = bool(t.shared)
+        self.n_src = int(t.n_src)
+        self.n_recv = int(t.n_recv)
+
+    # -- lifetime
+    def free(self):
+        if self._h is not None:
+            _lib().fmmds_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- raw views (device pointers)
+    def _t(self):
+        if self._h is None:
+            raise RuntimeError("tree already freed")
+        return self._h.contents
+
+    def level(self, s: int, l: int) -> Level:
+        if not 0 <= l <= self.depth:
+            raise IndexError(l)
+        return (self._t().src if s == SRC else self._t().recv)[l]
+
+    def n_boxes(self, s: int, l: int) -> int:
+        return int(self.level(s, l).n)
+
+    def _list(self, kind: int, l: int):
+        off, ent, nb, ne = _vp(), _vp(), _u32(), _u64()
+        f = _lib().fmmds_neighbors if kind == 2 else _lib().fmmds_interactions
+        st = f(self._h, l, C.byref(off), C.byref(ent), C.byref(nb), C.byref(ne))
+        if st != OK:
+            raise FmmdsError(st, "fmmds_neighbors" if kind == 2 else "fmmds_interactions")
+        return off.value, ent.value, nb.value, ne.value
+
+    def neighbors(self, l: int):
+        """(offsets_ptr, entries_ptr, n_recv_boxes, n_entries) of E2 at level l."""
+        return self._list(2, l)
+
+    def interactions(self, l: int):
+        """(offsets_ptr, entries_ptr, n_recv_boxes, n_entries) of E4 at level l."""
+        return self._list(4, l)
+
+    # -- host copies (for checks and small consumers)
+    def host_perm(self, s: int) -> np.ndarray:
+        _lib()
+        t = self._t()
+        return _device_to_host(t.src_perm if s == SRC else t.recv_perm,
+                               self.n_src if s == SRC else self.n_recv, np.uint32)
+
+    def host_sorted_xyz(self, s: int) -> np.ndarray:
+        _lib()
+        t = self._t()
+        n = self.n_src if s == SRC else self.n_recv
+        return _device_to_host(t.src_sorted_xyz if s == SRC else t.recv_sorted_xyz,
+                               3 * n, np.float32).reshape(n, 3)
+
+    def host_keys(self, s: int, l: int) -> np.ndarray:
+        lv = self.level(s, l)
+        return _device_to_host(lv.key, lv.n, np.uint64 if self.key_bits == 64 else np.uint32)
+
+    def host_begin(self, s: int, l: int) -> np.ndarray:
+        lv = self.level(s, l)
+        return _device_to_host(lv.begin, lv.n + 1, np.uint32)
+
+    def host_parent(self, s: int, l: int) -> np.ndarray:
+        lv = self.level(s, l)
+        if not lv.parent:
+            raise ValueError("no parent array at level 0")
+        return _device_to_host(lv.parent, lv.n, np.uint32)
+
+    def host_child(self, s: int, l: int) -> np.ndarray:
+        lv = self.level(s, l)
+        if not lv.child:
+            raise ValueError("no child array at the finest level")
+        return _device_to_host(lv.child, lv.n + 1, np.uint32)
+
+    def host_list(self, kind: int, l: int):
+        off, ent, nb, ne = self._list(kind, l)
+        return _device_to_host(off, nb + 1, np.uint32), _device_to_host(ent, ne, np.uint32)
+
+    def host_list_rows(self, kind: int, l: int, rows) -> list:
+        """Entries of selected receiver boxes only (sampled checks at full size)."""
+        off_p, ent_p, nb, ne = self._list(kind, l)
+        off = _device_to_host(off_p, nb + 1, np.uint32)
+        out = []
+        for r in rows:
+            a, b = int(off[r]), int(off[r + 1])
+            out.append(_device_to_host(ent_p + 4 * a, b - a, np.uint32))
+        return out
+
+
+def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int = 0,
+          stream=None, allocator: str = "pool") -> Tree:
+    """Build the FMM data structures on the GPU.
+
+    src, recv: torch float32 CUDA tensors of shape (n, 3), contiguous; recv
+    None means receivers are the sources. stream: a torch.cuda.Stream (default:
+    the current stream). allocator: "pool" (the library's stream-ordered pool)
+    or "torch" (torch's caching allocator)."""
+    import torch
+    L = _lib()
+    for name, x in (("src", src), ("recv", recv)):
+        if x is None:
+            continue
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                and x.dim() == 2 and x.shape[1] == 3 and x.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor of shape (n, 3)")
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    opt = Options()
+    opt.key_bits, opt.cluster_s, opt.max_level, opt.reserved = key_bits, cluster_s, max_level, 0
+    opt.stream = s.cuda_stream
+    keep = None
+    if allocator == "torch":
+        global _TORCH_ALLOC
+        if _TORCH_ALLOC is None:
+            _TORCH_ALLOC = _TorchAllocator()
+        keep = _TORCH_ALLOC
+        opt.alloc, opt.release = keep.alloc, keep.release
+    elif allocator != "pool":
+        raise ValueError(allocator)
+    out = C.POINTER(TreeStruct)()
+    st = L.fmmds_build(src.data_ptr(), src.shape[0],
+                       None if recv is None else recv.data_ptr(),
+                       0 if recv is None else recv.shape[0], C.byref(opt), C.byref(out))
+    if st != OK:
+        raise FmmdsError(st, "fmmds_build")
+    return Tree(out, keep)

@@ -1,0 +1,114 @@
+// Device-side helpers shared by the gfx950 kernels of libfmmds.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmmds {
+
+// ---------------------------------------------------------------------------
+// Morton index arithmetic (Section 2.4: bit b of the box coordinates x, y, z
+// sits at bit 3b, 3b+1, 3b+2 of the index; Section 3.4: interleave and
+// deinterleave). Magic-mask bit spreading, 21 bits per axis.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x001f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x001f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x00000000001fffffull;
+  return (uint32_t)x;
+}
+
+// 10-bit-per-axis variants for keys of at most 30 bits.
+__device__ __forceinline__ uint32_t spread3_10(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 primitives.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `m` at lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back (single-pass chained scan). A status word holds a
+// 2-bit state in bits 62..63 and a 62-bit running count: 0 = not ready,
+// 1 = this tile's aggregate only, 2 = inclusive prefix up to this tile.
+// Tiles take their id from an atomic ticket, so every tile a waiter looks
+// back at has already been scheduled and will publish.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStInc = 2ull << 62;
+constexpr uint64_t kStVal = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish `agg` for `tile` in the status column starting at `col` with
+// `stride` words between consecutive tiles; return the exclusive prefix.
+__device__ __forceinline__ uint64_t lookback(uint64_t* col, uint64_t stride, uint32_t tile,
+                                             uint64_t agg) {
+  if (tile == 0) {
+    st_status(col, kStInc | agg);
+    return 0;
+  }
+  st_status(col + (uint64_t)tile * stride, kStAgg | agg);
+  uint64_t excl = 0;
+  int64_t t = (int64_t)tile - 1;
+  while (true) {
+    const uint64_t s = ld_status(col + (uint64_t)t * stride);
+    const uint64_t f = s >> 62;
+    if (f == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & kStVal;
+    if (f == 2) break;
+    --t;
+  }
+  st_status(col + (uint64_t)tile * stride, kStInc | (excl + agg));
+  return excl;
+}
+
+}  // namespace fmmds

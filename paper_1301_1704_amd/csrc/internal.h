@@ -1,0 +1,82 @@
+// Host-side declarations shared by the translation units of libfmmds.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fmmds {
+
+constexpr int kMaxLevel = 21;
+constexpr int kMaxPasses = 8;  // 63 key bits / 8-bit digits
+
+// Tile shapes of the single-pass kernels.
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 elements
+constexpr int kCompBlock = 256;
+constexpr int kCompItems = 8;
+constexpr int kCompTile = kCompBlock * kCompItems;  // 2048 elements
+
+inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Small per-build block in device memory, zeroed at the start of a build and
+// read back by the host at its synchronization points.
+struct DevMeta {
+  uint32_t err_range;
+  uint32_t overflow;
+  uint32_t n_boxes[2][kMaxLevel + 1];
+  uint32_t max_occ[2][kMaxLevel + 1];
+  uint64_t list_total[2][kMaxLevel + 1];  // [0] = E2, [1] = E4
+};
+
+// Sort elements: with `packed`, one uint64 holding (key << 32 | index) for keys
+// of at most 32 bits; otherwise a uint64 key array plus a uint32 index array.
+struct SortBufs {
+  uint64_t* k[2];
+  uint32_t* v[2];
+};
+
+// ---- sort.hip
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
+                   uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err, hipStream_t s);
+void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass, hipStream_t s);
+void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                      uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s);
+
+// ---- tables.hip
+void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
+                 const float* xyz, uint32_t n, uint32_t* perm, float* sorted_xyz, void* leaf_key,
+                 uint32_t* leaf_begin, uint64_t* status, uint32_t* tile_counter, uint32_t* n_out,
+                 hipStream_t s);
+void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32_t* n_in,
+                  uint32_t cap_in, uint32_t n_points, void* kout, uint32_t* bout, uint32_t* cout,
+                  uint8_t* mout, uint32_t* pout, uint64_t* status, uint32_t* tile_counter,
+                  uint32_t* n_out, hipStream_t s);
+void launch_max_occupancy(const uint32_t* begin, const uint32_t* n_in, uint32_t cap,
+                          uint32_t* out, hipStream_t s);
+
+// ---- lists.hip
+struct ListLevelArgs {
+  uint32_t level;
+  uint32_t n_recv;             // receiver boxes at `level`
+  const void* recv_key;        // level
+  const uint32_t* recv_parent; // level
+  const void* src_key_up;      // level - 1
+  const uint8_t* src_mask_up;  // level - 1
+  const uint32_t* src_child_up;// level - 1
+  const uint32_t* e2_off_up;   // level - 1 (unused when up_all)
+  const uint32_t* e2_ent_up;
+  uint32_t up_all;             // level - 1 == 1: E2 there is every source box
+  uint32_t n_src_up;           // source boxes at level - 1
+};
+void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
+                       hipStream_t s);
+void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
+                      const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s);
+void launch_scan_counts(const uint32_t* cnt, uint32_t n, uint32_t* off, uint64_t* total,
+                        uint32_t* overflow, uint64_t* status, uint32_t* tile_counter,
+                        hipStream_t s);
+
+}  // namespace fmmds

@@ -1,0 +1,639 @@
+// Host orchestration of fmmds_build and the rest of the C ABI (include/fmmds.h).
+//
+// One build enqueues, per point set, on the caller's stream:
+//   keygen + digit histograms -> radix passes -> permute + leaf compaction ->
+//   levels max_level-1 .. 0 (+ occupancy maxima when the depth rule is on),
+// then reads a small metadata block back (box counts, range flag, maxima),
+// chooses the depth, and builds the lists level by level: count, scan, read
+// the list totals back, allocate exactly, fill. All compute runs in the HIP
+// kernels of sort.hip, tables.hip and lists.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fmmds.h"
+#include "internal.h"
+
+namespace fmmds {
+namespace {
+
+struct Fail {
+  fmmds_status st;
+};
+
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw Fail{FMMDS_ERR_DEVICE};
+}
+inline void ck_launch() { ck(hipGetLastError()); }
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device memory through the caller's allocator, or the stream-ordered pool.
+struct Allocator {
+  fmmds_alloc_fn alloc = nullptr;
+  fmmds_release_fn release = nullptr;
+  void* ctx = nullptr;
+  hipStream_t stream = nullptr;
+
+  void* get(size_t bytes) {
+    bytes = round_up(std::max<size_t>(bytes, 1), 256);
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(ctx, bytes, (void*)stream);
+    } else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (!p) throw Fail{FMMDS_ERR_NOMEM};
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    bytes = round_up(std::max<size_t>(bytes, 1), 256);
+    if (release) release(ctx, p, bytes, (void*)stream);
+    else (void)hipFreeAsync(p, stream);
+  }
+};
+
+struct Block {
+  void* p;
+  size_t bytes;
+};
+
+// A set of allocations released together.
+struct Pool {
+  Allocator* A = nullptr;
+  std::vector<Block> blocks;
+  template <typename T>
+  T* get(size_t count) {
+    const size_t bytes = count * sizeof(T);
+    void* p = A->get(bytes);
+    blocks.push_back({p, bytes});
+    return (T*)p;
+  }
+  void release_all() {
+    for (auto it = blocks.rbegin(); it != blocks.rend(); ++it) A->put(it->p, it->bytes);
+    blocks.clear();
+  }
+};
+
+// Bump allocation of zeroed look-back status words and tile tickets.
+struct StatusArena {
+  uint64_t* words = nullptr;
+  size_t n_words = 0, used_words = 0;
+  uint32_t* tickets = nullptr;
+  size_t n_tickets = 0, used_tickets = 0;
+  uint64_t* take_words(size_t n) {
+    if (used_words + n > n_words) throw Fail{FMMDS_ERR_DEVICE};
+    uint64_t* p = words + used_words;
+    used_words += n;
+    return p;
+  }
+  uint32_t* take_ticket() {
+    if (used_tickets >= n_tickets) throw Fail{FMMDS_ERR_DEVICE};
+    return tickets + used_tickets++;
+  }
+};
+
+struct LevelBufs {
+  void* key = nullptr;
+  uint32_t* begin = nullptr;
+  uint32_t* parent = nullptr;
+  uint32_t* child = nullptr;
+  uint8_t* mask = nullptr;
+  uint32_t cap = 0;
+};
+
+struct SetBufs {
+  const float* xyz = nullptr;
+  uint32_t n = 0;
+  uint32_t* perm = nullptr;
+  float* sorted_xyz = nullptr;
+  LevelBufs lv[kMaxLevel + 1];
+};
+
+struct ListBufs {
+  uint32_t* off[2] = {nullptr, nullptr};
+  uint32_t* ent[2] = {nullptr, nullptr};
+  uint64_t total[2] = {0, 0};
+};
+
+struct TreeImpl {
+  Allocator A;
+  Pool outs;
+  ListBufs lists[kMaxLevel + 1];
+  uint32_t n_recv_boxes[kMaxLevel + 1] = {};
+};
+
+bool g_pool_configured[64] = {};
+
+void configure_default_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  if (g_pool_configured[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = ~0ull;  // keep freed blocks cached for the next build
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+  g_pool_configured[dev] = true;
+}
+
+uint32_t level_cap(uint32_t n, uint32_t l) {
+  const uint64_t boxes = 1ull << (3 * l);
+  return (uint32_t)std::min<uint64_t>(n, boxes);
+}
+
+// Host copy of the metadata block, through a pinned buffer of this thread.
+DevMeta* host_meta() {
+  thread_local DevMeta* h = nullptr;
+  if (!h) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(DevMeta), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{FMMDS_ERR_NOMEM};
+    }
+    h = (DevMeta*)p;
+  }
+  return h;
+}
+
+void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
+  ck(hipMemcpyAsync(h, d, sizeof(DevMeta), hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
+}
+
+
+// ---------------------------------------------------------------------------
+// Per-kernel event timing (fmmds_profile_*).
+// ---------------------------------------------------------------------------
+enum KernelClass {
+  K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
+  K_NCLASS
+};
+const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
+                                          "sort_pass", "leaf",        "level",
+                                          "max_occupancy", "list_count", "scan_counts",
+                                          "list_fill"};
+
+struct ClassStat {
+  uint64_t launches = 0;
+  double ms = 0, bytes = 0;
+};
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+ClassStat g_prof[K_NCLASS];
+std::vector<hipEvent_t> g_events;  // reusable, guarded by g_prof_mu
+
+struct Prof {
+  bool on = false;
+  hipStream_t s = nullptr;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+    int set, level;  // for launches whose bytes depend on box counts
+  };
+  std::vector<Rec> recs;
+
+  hipEvent_t ev() {
+    {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      if (!g_events.empty()) {
+        hipEvent_t e = g_events.back();
+        g_events.pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e;
+    ck(hipEventCreate(&e));
+    return e;
+  }
+  template <typename F>
+  void run(int cls, double bytes, F&& f, int set = -1, int level = -1) {
+    if (!on) {
+      f();
+      ck_launch();
+      return;
+    }
+    hipEvent_t a = ev(), b = ev();
+    ck(hipEventRecord(a, s));
+    f();
+    ck_launch();
+    ck(hipEventRecord(b, s));
+    recs.push_back({cls, a, b, bytes, set, level});
+  }
+  // `extra(rec)` adds bytes known only after the launch (box counts).
+  template <typename X>
+  void finish(X&& extra) {
+    if (!on) return;
+    ck(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (Rec& r : recs) {
+      float ms = 0;
+      ck(hipEventElapsedTime(&ms, r.a, r.b));
+      g_prof[r.cls].launches += 1;
+      g_prof[r.cls].ms += ms;
+      g_prof[r.cls].bytes += r.bytes + extra(r);
+      g_events.push_back(r.a);
+      g_events.push_back(r.b);
+    }
+    recs.clear();
+  }
+  void drop() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (Rec& r : recs) {
+      g_events.push_back(r.a);
+      g_events.push_back(r.b);
+    }
+    recs.clear();
+  }
+};
+
+fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, uint32_t n_recv,
+                   const fmmds_options* opt, fmmds_tree** out) {
+  const bool shared = recv_xyz == nullptr;
+  if (shared) n_recv = n_src;
+  if (!src_xyz || !opt || n_src == 0 || n_recv == 0 || n_src >= 0xFFFFFFFFu ||
+      n_recv >= 0xFFFFFFFFu)
+    return FMMDS_ERR_ARG;
+  if (opt->key_bits != 32 && opt->key_bits != 64) return FMMDS_ERR_ARG;
+  if (opt->max_level < 2 || opt->max_level > opt->key_bits / 3) return FMMDS_ERR_ARG;
+  if (opt->reserved != 0 || ((opt->alloc == nullptr) != (opt->release == nullptr)))
+    return FMMDS_ERR_ARG;
+
+  const uint32_t L = opt->max_level;
+  const bool key64 = opt->key_bits == 64;
+  const bool packed = 3 * L <= 32;
+  const uint32_t n_pass = div_up(3 * L, 8);
+  const uint32_t ksz = key64 ? 8 : 4;
+  const int nsets = shared ? 1 : 2;
+
+  TreeImpl* impl = new (std::nothrow) TreeImpl();
+  fmmds_tree* t = new (std::nothrow) fmmds_tree();
+  if (!impl || !t) {
+    delete impl;
+    delete t;
+    return FMMDS_ERR_NOMEM;
+  }
+  std::memset(t, 0, sizeof(*t));
+  impl->A.alloc = opt->alloc;
+  impl->A.release = opt->release;
+  impl->A.ctx = opt->alloc_ctx;
+  impl->A.stream = (hipStream_t)opt->stream;
+  impl->outs.A = &impl->A;
+  Pool temps;
+  temps.A = &impl->A;
+  const hipStream_t st = impl->A.stream;
+
+  fmmds_status result = FMMDS_OK;
+  Prof P;
+  P.on = g_prof_on.load() != 0;
+  P.s = st;
+  try {
+    if (!opt->alloc) configure_default_pool();
+    SetBufs sets[2];
+    sets[0].xyz = src_xyz;
+    sets[0].n = n_src;
+    sets[1].xyz = shared ? src_xyz : recv_xyz;
+    sets[1].n = n_recv;
+
+    // ---- workspace: metadata, histograms, digit offsets, status words
+    size_t words = 0, tickets = 0;
+    for (int s = 0; s < nsets; ++s) {
+      const uint32_t n = sets[s].n;
+      words += (size_t)n_pass * div_up(n, kSortTile) * 256 + div_up(n, kCompTile);
+      for (uint32_t l = 0; l < L; ++l) words += div_up(level_cap(n, l + 1), kCompTile);
+      tickets += n_pass + 1 + L;
+    }
+    const size_t meta_b = round_up(sizeof(DevMeta), 256);
+    const size_t hist_b = round_up(2 * kMaxPasses * 256 * 4, 256);
+    const size_t tick_b = round_up(tickets * 4, 256);
+    const size_t ws_b = round_up(meta_b + 2 * hist_b + tick_b + words * 8, 256);
+    char* ws = temps.get<char>(ws_b);
+    DevMeta* meta = (DevMeta*)ws;
+    uint32_t* hist = (uint32_t*)(ws + meta_b);
+    uint32_t* goff = (uint32_t*)(ws + meta_b + hist_b);
+    StatusArena sa;
+    sa.tickets = (uint32_t*)(ws + meta_b + 2 * hist_b);
+    sa.n_tickets = tickets;
+    sa.words = (uint64_t*)(ws + meta_b + 2 * hist_b + tick_b);
+    sa.n_words = words;
+    P.run(K_ZERO, (double)ws_b, [&] { launch_zero(ws, ws_b, st); });
+    const uint32_t n_max = std::max(sets[0].n, sets[nsets - 1].n);
+    SortBufs sb{};
+    sb.k[0] = temps.get<uint64_t>(n_max);
+    sb.k[1] = temps.get<uint64_t>(n_max);
+    if (!packed) {
+      sb.v[0] = temps.get<uint32_t>(n_max);
+      sb.v[1] = temps.get<uint32_t>(n_max);
+    }
+
+    for (int s = 0; s < nsets; ++s) {
+      SetBufs& S = sets[s];
+      const uint32_t n = S.n;
+      S.perm = impl->outs.get<uint32_t>(n);
+      S.sorted_xyz = impl->outs.get<float>(3 * (size_t)n);
+      // Tables, sized for the worst case so no host round trip is needed.
+      size_t tb = 0;
+      for (uint32_t l = 0; l <= L; ++l) {
+        const size_t c = level_cap(n, l);
+        tb += round_up(c * ksz, 256) + round_up((c + 1) * 4, 256);
+        if (l >= 1) tb += round_up(c * 4, 256);
+        if (l < L) tb += round_up((c + 1) * 4, 256) + round_up(c, 256);
+      }
+      char* tp = impl->outs.get<char>(tb);
+      for (uint32_t l = 0; l <= L; ++l) {
+        LevelBufs& B = S.lv[l];
+        const size_t c = level_cap(n, l);
+        B.cap = (uint32_t)c;
+        B.key = tp;
+        tp += round_up(c * ksz, 256);
+        B.begin = (uint32_t*)tp;
+        tp += round_up((c + 1) * 4, 256);
+        if (l >= 1) {
+          B.parent = (uint32_t*)tp;
+          tp += round_up(c * 4, 256);
+        }
+        if (l < L) {
+          B.child = (uint32_t*)tp;
+          tp += round_up((c + 1) * 4, 256);
+          B.mask = (uint8_t*)tp;
+          tp += round_up(c, 256);
+        }
+      }
+
+      // ---- keys and sort
+      uint32_t* h = hist + s * kMaxPasses * 256;
+      uint32_t* g = goff + s * kMaxPasses * 256;
+      P.run(K_KEYGEN, (double)n * (12 + 8 + (packed ? 0 : 4)), [&] {
+        launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
+      });
+      P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+      for (uint32_t p = 0; p < n_pass; ++p) {
+        const int a = p & 1, b = a ^ 1;
+        const uint32_t shift = (packed ? 32 : 0) + 8 * p;
+        uint64_t* stw = sa.take_words((size_t)div_up(n, kSortTile) * 256);
+        uint32_t* tk = sa.take_ticket();
+        P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
+          launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,
+                           stw, tk, st);
+        });
+      }
+      const int fin = n_pass & 1;
+
+      // ---- leaf level, then coarser levels
+      {
+        uint64_t* stw = sa.take_words(div_up(n, kCompTile));
+        uint32_t* tk = sa.take_ticket();
+        // sorted pairs in, permutation + gathered and written coordinates out;
+        // leaf keys and bookmarks are added once the box count is known
+        P.run(K_LEAF, (double)n * ((packed ? 8 : 12) + 4 + 12 + 12), [&] {
+          launch_leaf(packed, key64, sb.k[fin], sb.v[fin], S.xyz, n, S.perm, S.sorted_xyz,
+                      S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L], st);
+        }, s, (int)L);
+      }
+      for (int l = (int)L - 1; l >= 0; --l) {
+        LevelBufs& up = S.lv[l];
+        LevelBufs& dn = S.lv[l + 1];
+        uint64_t* stw = sa.take_words(div_up(dn.cap, kCompTile));
+        uint32_t* tk = sa.take_ticket();
+        P.run(K_LEVEL, 0.0, [&] {
+          launch_level(key64, dn.key, dn.begin, &meta->n_boxes[s][l + 1], dn.cap, n, up.key,
+                       up.begin, up.child, up.mask, dn.parent, stw, tk, &meta->n_boxes[s][l],
+                       st);
+        }, s, l);
+      }
+      if (opt->cluster_s > 0) {
+        for (uint32_t l = 2; l <= L; ++l) {
+          P.run(K_MAXOCC, 0.0, [&] {
+            launch_max_occupancy(S.lv[l].begin, &meta->n_boxes[s][l], S.lv[l].cap,
+                                 &meta->max_occ[s][l], st);
+          }, s, (int)l);
+        }
+      }
+    }
+
+    // ---- sync point 1: box counts, range flag, occupancy maxima
+    DevMeta* hm = host_meta();
+    fetch_meta(meta, hm, st);
+    if (hm->err_range) throw Fail{FMMDS_ERR_RANGE};
+    const int rs = shared ? 0 : 1;
+    uint32_t D = L;
+    if (opt->cluster_s > 0) {
+      for (uint32_t l = 2; l <= L; ++l) {
+        if (hm->max_occ[0][l] <= opt->cluster_s && hm->max_occ[rs][l] <= opt->cluster_s) {
+          D = l;
+          break;
+        }
+      }
+    }
+    uint32_t nb[2][kMaxLevel + 1];
+    for (int s = 0; s < 2; ++s)
+      for (uint32_t l = 0; l <= L; ++l) nb[s][l] = hm->n_boxes[s < nsets ? s : 0][l];
+
+    // ---- lists, levels 2..D
+    size_t lwords = 0, lmax = 0;
+    for (uint32_t l = 2; l <= D; ++l) {
+      lwords += 2 * (size_t)div_up(nb[rs][l], kCompTile);
+      lmax = std::max<size_t>(lmax, nb[rs][l]);
+    }
+    const size_t ltick_b = round_up(2 * (kMaxLevel + 1) * 4, 256);
+    const size_t lws_b = round_up(ltick_b + lwords * 8, 256);
+    char* lws = temps.get<char>(lws_b);
+    StatusArena la;
+    la.tickets = (uint32_t*)lws;
+    la.n_tickets = 2 * (kMaxLevel + 1);
+    la.words = (uint64_t*)(lws + ltick_b);
+    la.n_words = lwords;
+    P.run(K_ZERO, (double)lws_b, [&] { launch_zero(lws, lws_b, st); });
+    uint32_t* cnt = temps.get<uint32_t>(2 * std::max<size_t>(lmax, 1));
+    for (uint32_t l = 2; l <= D; ++l) {
+      const uint32_t nr = nb[rs][l];
+      ListLevelArgs a{};
+      a.level = l;
+      a.n_recv = nr;
+      a.recv_key = sets[rs].lv[l].key;
+      a.recv_parent = sets[rs].lv[l].parent;
+      a.src_key_up = sets[0].lv[l - 1].key;
+      a.src_mask_up = sets[0].lv[l - 1].mask;
+      a.src_child_up = sets[0].lv[l - 1].child;
+      a.up_all = (l - 1 == 1) ? 1u : 0u;
+      a.n_src_up = nb[0][l - 1];
+      if (!a.up_all) {
+        a.e2_off_up = impl->lists[l - 1].off[0];
+        a.e2_ent_up = impl->lists[l - 1].ent[0];
+      }
+      ListBufs& LB = impl->lists[l];
+      // receiver key + parent in, two counts out; the parent lists and the
+      // parent-level source keys, masks and first children read once
+      const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
+      const double side = (double)nr * (ksz + 4) + e2up * 4 + (double)nb[0][l - 1] * (ksz + 5);
+      P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + nr, st); });
+      for (int k = 0; k < 2; ++k) {
+        LB.off[k] = impl->outs.get<uint32_t>((size_t)nr + 1);
+        uint64_t* stw = la.take_words(div_up(nr, kCompTile));
+        uint32_t* tk = la.take_ticket();
+        P.run(K_SCAN, (double)nr * 8 + 4, [&] {
+          launch_scan_counts(cnt + (size_t)k * nr, nr, LB.off[k], &meta->list_total[k][l],
+                             &meta->overflow, stw, tk, st);
+        });
+      }
+      fetch_meta(meta, hm, st);  // sync point: this level's list totals
+      if (hm->overflow) throw Fail{FMMDS_ERR_OVERFLOW};
+      for (int k = 0; k < 2; ++k) {
+        LB.total[k] = hm->list_total[k][l];
+        LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
+      }
+      P.run(K_FILL, side + (double)nr * 8 + 4.0 * (double)(LB.total[0] + LB.total[1]), [&] {
+        launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st);
+      });
+      impl->n_recv_boxes[l] = nr;
+    }
+
+    // Box-count-dependent bytes: leaf keys + bookmarks; a coarser level reads
+    // the finer keys and bookmarks and writes keys, bookmarks, first children,
+    // masks and the finer level's parents; the occupancy pass reads bookmarks.
+    P.finish([&](const Prof::Rec& r) -> double {
+      if (r.set < 0) return 0.0;
+      const uint32_t* c = nb[r.set == 0 ? 0 : rs];
+      if (r.cls == K_LEAF) return (double)c[r.level] * (ksz + 4);
+      if (r.cls == K_LEVEL)
+        return (double)c[r.level + 1] * (ksz + 4 + 4) + (double)c[r.level] * (ksz + 4 + 4 + 1);
+      if (r.cls == K_MAXOCC) return (double)(c[r.level] + 1) * 4;
+      return 0.0;
+    });
+
+    // ---- public view
+    t->depth = D;
+    t->key_bits = opt->key_bits;
+    t->max_level = L;
+    t->shared = shared ? 1u : 0u;
+    t->n_src = n_src;
+    t->n_recv = n_recv;
+    t->src_perm = sets[0].perm;
+    t->src_sorted_xyz = sets[0].sorted_xyz;
+    t->recv_perm = sets[rs].perm;
+    t->recv_sorted_xyz = sets[rs].sorted_xyz;
+    for (int s = 0; s < 2; ++s) {
+      const SetBufs& S = sets[s == 0 ? 0 : rs];
+      fmmds_level* lv = s == 0 ? t->src : t->recv;
+      for (uint32_t l = 0; l <= D; ++l) {
+        lv[l].n = nb[s == 0 ? 0 : rs][l];
+        lv[l].key = S.lv[l].key;
+        lv[l].begin = S.lv[l].begin;
+        lv[l].parent = l >= 1 ? S.lv[l].parent : nullptr;
+        lv[l].child = l < D ? S.lv[l].child : nullptr;
+      }
+    }
+    t->impl = impl;
+    temps.release_all();
+  } catch (const Fail& f) {
+    result = f.st;
+  } catch (const std::bad_alloc&) {
+    result = FMMDS_ERR_NOMEM;
+  }
+  if (result != FMMDS_OK) {
+    (void)hipGetLastError();
+    P.drop();
+    temps.release_all();
+    impl->outs.release_all();
+    delete impl;
+    delete t;
+    return result;
+  }
+  *out = t;
+  return FMMDS_OK;
+}
+
+fmmds_status list_query(const fmmds_tree* t, int kind, uint32_t level, const uint32_t** offsets,
+                        const uint32_t** entries, uint32_t* n_recv_boxes, uint64_t* n_entries) {
+  if (!t || !t->impl || !offsets || !entries || !n_recv_boxes || !n_entries) return FMMDS_ERR_ARG;
+  if (level < 2 || level > t->depth) return FMMDS_ERR_LEVEL;
+  const TreeImpl* impl = (const TreeImpl*)t->impl;
+  const ListBufs& LB = impl->lists[level];
+  *offsets = LB.off[kind];
+  *entries = LB.ent[kind];
+  *n_recv_boxes = impl->n_recv_boxes[level];
+  *n_entries = LB.total[kind];
+  return FMMDS_OK;
+}
+
+}  // namespace
+}  // namespace fmmds
+
+extern "C" {
+
+fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
+                         uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out) {
+  if (!out) return FMMDS_ERR_ARG;
+  *out = nullptr;
+  return fmmds::build(src_xyz, n_src, recv_xyz, n_recv, opt, out);
+}
+
+fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
+                             const uint32_t** entries, uint32_t* n_recv_boxes,
+                             uint64_t* n_entries) {
+  return fmmds::list_query(t, 0, level, offsets, entries, n_recv_boxes, n_entries);
+}
+
+fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
+                                const uint32_t** entries, uint32_t* n_recv_boxes,
+                                uint64_t* n_entries) {
+  return fmmds::list_query(t, 1, level, offsets, entries, n_recv_boxes, n_entries);
+}
+
+void fmmds_free(fmmds_tree* t) {
+  if (!t) return;
+  fmmds::TreeImpl* impl = (fmmds::TreeImpl*)t->impl;
+  if (impl) {
+    impl->outs.release_all();
+    delete impl;
+  }
+  delete t;
+}
+
+void fmmds_profile_enable(int on) { fmmds::g_prof_on.store(on ? 1 : 0); }
+
+void fmmds_profile_reset(void) {
+  std::lock_guard<std::mutex> g(fmmds::g_prof_mu);
+  for (auto& c : fmmds::g_prof) c = fmmds::ClassStat();
+}
+
+uint32_t fmmds_profile_read(fmmds_kernel_stat* out, uint32_t cap) {
+  std::lock_guard<std::mutex> g(fmmds::g_prof_mu);
+  uint32_t n = 0;
+  for (int k = 0; k < fmmds::K_NCLASS; ++k) {
+    if (fmmds::g_prof[k].launches == 0) continue;
+    if (out && n < cap) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, fmmds::kClassName[k], sizeof(out[n].name) - 1);
+      out[n].launches = fmmds::g_prof[k].launches;
+      out[n].total_ms = fmmds::g_prof[k].ms;
+      out[n].bytes = fmmds::g_prof[k].bytes;
+    }
+    ++n;
+  }
+  return n;
+}
+
+const char* fmmds_status_string(fmmds_status s) {
+  switch (s) {
+    case FMMDS_OK: return "ok";
+    case FMMDS_ERR_ARG: return "invalid argument";
+    case FMMDS_ERR_RANGE: return "coordinate outside [0, 1)";
+    case FMMDS_ERR_NOMEM: return "out of device memory";
+    case FMMDS_ERR_DEVICE: return "HIP runtime error";
+    case FMMDS_ERR_LEVEL: return "level outside [2, depth]";
+    case FMMDS_ERR_OVERFLOW: return "list too long for 32-bit offsets";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

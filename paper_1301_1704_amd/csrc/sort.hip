@@ -1,0 +1,231 @@
+// Key generation and LSD radix sort of (Morton key, point index) pairs.
+//
+// The paper reorders points by the Morton index of their finest-level box
+// with a histogram pseudo-sort whose order inside a box depends on atomic
+// timing (Section 3.1, Algorithm 1). This library needs a deterministic order,
+// so it sorts (key, original index) pairs stably: an LSD radix sort with 8-bit
+// digits, one single-pass "chained scan" kernel per digit.
+#include "device.h"
+#include "internal.h"
+
+namespace fmmds {
+
+// ---------------------------------------------------------------------------
+// Zero fill (a kernel, so that it can sit inside a captured graph).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, size_t n16) {
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+    p[i] = z;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  // Every region handed to this function is 16-byte aligned and sized.
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return;
+  const uint32_t grid = (uint32_t)std::min<size_t>(div_up(n16, 256), 4096);
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint4*)p, n16);
+}
+
+// ---------------------------------------------------------------------------
+// K1: Morton key of every point (Section 2.4 box index, Section 3.4
+// interleave) plus the digit histograms of every sort pass.
+//
+// A point (x, y, z) is in the box floor(x * 2^L) per axis; x * 2^L is exact in
+// FP32. Coordinates outside [0, 1) (or NaN) raise the range flag; such points
+// get box 0 so that later kernels stay in bounds, and the build reports the
+// error.
+// ---------------------------------------------------------------------------
+struct P3 {
+  float x, y, z;
+};
+
+template <bool PACKED>
+__global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint32_t n, uint32_t L,
+                                                uint64_t* __restrict__ keys,
+                                                uint32_t* __restrict__ vals, uint32_t n_pass,
+                                                uint32_t* __restrict__ hist,
+                                                uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_hist[kMaxPasses * 256];
+  for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
+  __syncthreads();
+  const float scale = (float)(1u << L);
+  const uint32_t qmax = (1u << L) - 1;
+  bool bad = false;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
+    const P3 p = xyz[i];
+    const bool ok = (p.x >= 0.0f && p.x < 1.0f) && (p.y >= 0.0f && p.y < 1.0f) &&
+                    (p.z >= 0.0f && p.z < 1.0f);
+    bad |= !ok;
+    uint32_t qx = 0, qy = 0, qz = 0;
+    if (ok) {
+      qx = min((uint32_t)floorf(p.x * scale), qmax);
+      qy = min((uint32_t)floorf(p.y * scale), qmax);
+      qz = min((uint32_t)floorf(p.z * scale), qmax);
+    }
+    uint64_t key;
+    if (PACKED) {
+      key = spread3_10(qx) | (spread3_10(qy) << 1) | (spread3_10(qz) << 2);
+      keys[i] = (key << 32) | (uint32_t)i;
+    } else {
+      key = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+      keys[i] = key;
+      vals[i] = (uint32_t)i;
+    }
+    for (uint32_t p8 = 0; p8 < n_pass; ++p8)
+      atomicAdd(&s_hist[p8 * 256 + ((key >> (8 * p8)) & 0xFF)], 1u);
+  }
+  if (bad) atomicOr(err, 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256)
+    if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+}
+
+void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
+                   uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
+                   hipStream_t s) {
+  const uint32_t grid = std::min<uint32_t>(div_up(n, 256), 2048);
+  if (packed)
+    hipLaunchKernelGGL(k_keygen<true>, dim3(grid), dim3(256), 0, s, (const P3*)xyz, n, L, keys,
+                       vals, n_pass, hist, err);
+  else
+    hipLaunchKernelGGL(k_keygen<false>, dim3(grid), dim3(256), 0, s, (const P3*)xyz, n, L, keys,
+                       vals, n_pass, hist, err);
+}
+
+// Exclusive scan of each pass's 256-bin histogram: where digit d starts.
+__global__ __launch_bounds__(256) void k_digit_offsets(const uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ goff) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t p = blockIdx.x, d = threadIdx.x, lane = d & 63, w = d >> 6;
+  const uint32_t c = hist[p * 256 + d];
+  const uint32_t inc = wave_incl_scan(c);
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < w; ++i) base += s_w[i];
+  goff[p * 256 + d] = base + inc - c;
+}
+
+void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_digit_offsets, dim3(n_pass), dim3(256), 0, s, hist, goff);
+}
+
+// ---------------------------------------------------------------------------
+// K2: one stable LSD pass on the 8-bit digit at `shift`.
+//
+// A tile of 4096 elements is split into four contiguous 1024-element wave
+// segments, loaded 64 at a time (coalesced). Each wave ranks its elements by
+// digit with eight ballots per element (lanes whose digit agrees on every
+// bit), keeping running per-digit counts in LDS, so ranks follow input order.
+// The tile's 256 digit counts are then chained across tiles by decoupled
+// look-back (thread d owns digit d), the tile is staged in LDS in digit order,
+// and written out so that consecutive threads store consecutive addresses of
+// one digit's run.
+// ---------------------------------------------------------------------------
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kSortWSeg = 64 * kSortItems;
+
+template <bool PACKED>
+__global__ __launch_bounds__(kSortBlock) void k_sort_pass(
+    const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ vout, uint32_t n, uint32_t shift, const uint32_t* __restrict__ goff,
+    uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter) {
+  __shared__ uint64_t s_key[kSortTile];
+  __shared__ uint32_t s_val[PACKED ? 1 : kSortTile];
+  __shared__ uint32_t s_hist[kSortWaves][256];
+  __shared__ uint32_t s_lstart[256];
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_scan[kSortWaves];
+  __shared__ uint32_t s_tile;
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (uint32_t i = tid; i < kSortWaves * 256; i += kSortBlock) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint64_t wbase = (uint64_t)tile * kSortTile + (uint64_t)w * kSortWSeg;
+
+  uint64_t k[kSortItems];
+  uint32_t v[kSortItems];
+  uint32_t r[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+    k[i] = e < n ? kin[e] : 0;
+    if (!PACKED) v[i] = e < n ? vin[e] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const bool valid = wbase + (uint64_t)i * 64 + lane < n;
+    const uint32_t d = (uint32_t)(k[i] >> shift) & 0xFFu;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t below = mbcnt(peers);
+    uint32_t prev = 0;
+    if (valid) prev = s_hist[w][d];
+    r[i] = prev + below;
+    if (valid && below == 0) s_hist[w][d] = prev + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // Thread tid owns digit tid: wave-exclusive prefixes, tile count, local start.
+  const uint32_t d = tid;
+  uint32_t run = 0;
+#pragma unroll
+  for (int ww = 0; ww < kSortWaves; ++ww) {
+    const uint32_t c = s_hist[ww][d];
+    s_hist[ww][d] = run;
+    run += c;
+  }
+  const uint32_t cnt = run;
+  const uint32_t inc = wave_incl_scan(cnt);
+  if (lane == 63) s_scan[w] = inc;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
+  const uint32_t lstart = wpre + inc - cnt;
+  s_lstart[d] = lstart;
+  const uint64_t excl = lookback(status + d, 256, tile, cnt);
+  s_base[d] = goff[d] + (uint32_t)excl - lstart;
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (wbase + (uint64_t)i * 64 + lane < n) {
+      const uint32_t dd = (uint32_t)(k[i] >> shift) & 0xFFu;
+      const uint32_t lp = s_lstart[dd] + s_hist[w][dd] + r[i];
+      s_key[lp] = k[i];
+      if (!PACKED) s_val[lp] = v[i];
+    }
+  }
+  __syncthreads();
+  const uint64_t tbase = (uint64_t)tile * kSortTile;
+  const uint32_t tcount = (uint32_t)min((uint64_t)kSortTile, (uint64_t)n - tbase);
+  for (uint32_t j = tid; j < tcount; j += kSortBlock) {
+    const uint64_t kk = s_key[j];
+    const uint32_t dd = (uint32_t)(kk >> shift) & 0xFFu;
+    const uint32_t g = s_base[dd] + j;
+    kout[g] = kk;
+    if (!PACKED) vout[g] = s_val[j];
+  }
+}
+
+void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                      uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s) {
+  const uint32_t grid = div_up(n, kSortTile);
+  if (packed)
+    hipLaunchKernelGGL(k_sort_pass<true>, dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin, vout,
+                       n, shift, goff, status, tile_counter);
+  else
+    hipLaunchKernelGGL(k_sort_pass<false>, dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin,
+                       vout, n, shift, goff, status, tile_counter);
+}
+
+}  // namespace fmmds

@@ -1,0 +1,225 @@
+// Nonempty-box tables: leaf boundary detection plus stream compaction, and the
+// coarser levels, parents, children and child masks.
+//
+// The paper scans a dense histogram of all 8^lmax boxes (Section 3.2,
+// Algorithm 3), which costs memory and time in the number of boxes. Here the
+// sorted keys already group the points by box, so a box starts wherever the
+// key differs from the previous one (adjacent difference) and the starts are
+// compacted with a single-pass scan: the cost follows the nonempty boxes only.
+// Coarser levels repeat this on the previous level's keys shifted right by 3
+// (the parent of a box is its Morton index shifted by one level, Section 4.2).
+#include "device.h"
+#include "internal.h"
+
+namespace fmmds {
+
+constexpr int kCompWaves = kCompBlock / 64;
+
+struct P3 {
+  float x, y, z;
+};
+
+// Chain the per-(item, wave) flag counts of a tile (in element order) across
+// tiles. On return s_cnt holds exclusive prefixes within the tile and the
+// result is the tile's exclusive prefix over all earlier tiles.
+__device__ __forceinline__ uint64_t tile_flags_prefix(uint32_t* s_cnt, uint64_t* s_excl,
+                                                      uint64_t* status, uint32_t tile) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t c = lane < kCompItems * kCompWaves ? s_cnt[lane] : 0;
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane < kCompItems * kCompWaves) s_cnt[lane] = inc - c;
+    const uint32_t total = __shfl(inc, 63, 64);
+    if (lane == 0) *s_excl = lookback(status, 1, tile, total);
+  }
+  __syncthreads();
+  return *s_excl;
+}
+
+// ---------------------------------------------------------------------------
+// K3 + K4: from the sorted (key, index) pairs write the permutation and the
+// reordered coordinates (Algorithm 5, steps 3 and 6: SortedSrc / SortedRecv
+// and RecvPermutationIdx) and compact the finest level's nonempty boxes: their
+// keys and bookmarks (Algorithm 3's NonEmptyIdx and Bookmark).
+// ---------------------------------------------------------------------------
+template <bool PACKED, typename KeyT>
+__global__ __launch_bounds__(kCompBlock) void k_leaf(
+    const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv, const P3* __restrict__ xyz,
+    uint32_t n, uint32_t* __restrict__ perm, P3* __restrict__ sorted_xyz,
+    KeyT* __restrict__ leaf_key, uint32_t* __restrict__ leaf_begin, uint64_t* __restrict__ status,
+    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ n_out) {
+  __shared__ uint32_t s_cnt[kCompItems * kCompWaves];
+  __shared__ uint64_t s_excl;
+  __shared__ uint32_t s_tile;
+  const uint32_t tid = threadIdx.x, w = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint64_t tbase = (uint64_t)tile * kCompTile;
+
+  uint64_t key[kCompItems];
+  uint32_t incl[kCompItems];
+  uint32_t flags = 0;
+#pragma unroll
+  for (int i = 0; i < kCompItems; ++i) {
+    const uint64_t e = tbase + (uint64_t)i * kCompBlock + tid;
+    const bool valid = e < n;
+    uint64_t kk = 0, kp = 0;
+    uint32_t idx = 0;
+    if (valid) {
+      const uint64_t el = sk[e];
+      kk = PACKED ? (el >> 32) : el;
+      idx = PACKED ? (uint32_t)el : sv[e];
+      if (e > 0) kp = PACKED ? (sk[e - 1] >> 32) : sk[e - 1];
+      perm[e] = idx;
+      sorted_xyz[e] = xyz[idx];
+    }
+    const bool f = valid && (e == 0 || kk != kp);
+    const uint64_t ball = __ballot(f);
+    incl[i] = mbcnt(ball) + (f ? 1u : 0u);
+    flags |= (f ? 1u : 0u) << i;
+    key[i] = kk;
+    if ((tid & 63) == 0) s_cnt[i * kCompWaves + w] = (uint32_t)__popcll(ball);
+  }
+  const uint64_t texcl = tile_flags_prefix(s_cnt, &s_excl, status, tile);
+#pragma unroll
+  for (int i = 0; i < kCompItems; ++i) {
+    const uint64_t e = tbase + (uint64_t)i * kCompBlock + tid;
+    const uint64_t rank_incl = texcl + s_cnt[i * kCompWaves + w] + incl[i];
+    if ((flags >> i) & 1u) {
+      leaf_key[rank_incl - 1] = (KeyT)key[i];
+      leaf_begin[rank_incl - 1] = (uint32_t)e;
+    }
+    if (e + 1 == n) {
+      leaf_begin[rank_incl] = n;
+      *n_out = (uint32_t)rank_incl;
+    }
+  }
+}
+
+void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
+                 const float* xyz, uint32_t n, uint32_t* perm, float* sorted_xyz, void* leaf_key,
+                 uint32_t* leaf_begin, uint64_t* status, uint32_t* tile_counter, uint32_t* n_out,
+                 hipStream_t s) {
+  const uint32_t grid = div_up(n, kCompTile);
+#define FMMDS_LEAF(P, K)                                                                         \
+  hipLaunchKernelGGL((k_leaf<P, K>), dim3(grid), dim3(kCompBlock), 0, s, sk, sv, (const P3*)xyz, \
+                     n, perm, (P3*)sorted_xyz, (K*)leaf_key, leaf_begin, status, tile_counter,    \
+                     n_out)
+  if (packed && key64) FMMDS_LEAF(true, uint64_t);
+  else if (packed) FMMDS_LEAF(true, uint32_t);
+  else if (key64) FMMDS_LEAF(false, uint64_t);
+  else FMMDS_LEAF(false, uint32_t);
+#undef FMMDS_LEAF
+}
+
+// ---------------------------------------------------------------------------
+// K5: level l from level l + 1. Box j of level l+1 starts a new parent when
+// its key >> 3 differs from box j-1's. Writes, at level l: keys, bookmarks
+// (the first child's bookmark), first-child ranks and the 8-bit mask of
+// occupied child octants; at level l+1: the parent rank of every box.
+// The number of level-(l+1) boxes is read on the device; the grid covers the
+// worst case and surplus tiles exit at once.
+// ---------------------------------------------------------------------------
+template <typename KeyT>
+__global__ __launch_bounds__(kCompBlock) void k_level(
+    const KeyT* __restrict__ kin, const uint32_t* __restrict__ bin,
+    const uint32_t* __restrict__ n_in_p, uint32_t n_points, KeyT* __restrict__ kout,
+    uint32_t* __restrict__ bout, uint32_t* __restrict__ cout, uint8_t* __restrict__ mout,
+    uint32_t* __restrict__ pout, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
+    uint32_t* __restrict__ n_out) {
+  __shared__ uint32_t s_cnt[kCompItems * kCompWaves];
+  __shared__ uint64_t s_excl;
+  __shared__ uint32_t s_tile;
+  const uint32_t tid = threadIdx.x, w = tid >> 6;
+  const uint32_t n_in = *n_in_p;
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint64_t tbase = (uint64_t)tile * kCompTile;
+  if (tbase >= n_in) return;  // whole block: no valid element in this tile
+
+  uint64_t pkey[kCompItems];
+  uint32_t incl[kCompItems];
+  uint32_t flags = 0;
+#pragma unroll
+  for (int i = 0; i < kCompItems; ++i) {
+    const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;
+    const bool valid = j < n_in;
+    uint64_t pk = 0, pp = 0;
+    if (valid) {
+      pk = (uint64_t)kin[j] >> 3;
+      if (j > 0) pp = (uint64_t)kin[j - 1] >> 3;
+    }
+    const bool f = valid && (j == 0 || pk != pp);
+    const uint64_t ball = __ballot(f);
+    incl[i] = mbcnt(ball) + (f ? 1u : 0u);
+    flags |= (f ? 1u : 0u) << i;
+    pkey[i] = pk;
+    if ((tid & 63) == 0) s_cnt[i * kCompWaves + w] = (uint32_t)__popcll(ball);
+  }
+  const uint64_t texcl = tile_flags_prefix(s_cnt, &s_excl, status, tile);
+#pragma unroll
+  for (int i = 0; i < kCompItems; ++i) {
+    const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;
+    if (j >= n_in) continue;
+    const uint32_t rank = (uint32_t)(texcl + s_cnt[i * kCompWaves + w] + incl[i] - 1);
+    pout[j] = rank;
+    if ((flags >> i) & 1u) {
+      kout[rank] = (KeyT)pkey[i];
+      bout[rank] = bin[j];
+      cout[rank] = (uint32_t)j;
+      uint32_t m = 0;
+      for (uint64_t t = j; t < n_in && t < j + 8; ++t) {
+        const uint64_t kt = kin[t];
+        if ((kt >> 3) != pkey[i]) break;
+        m |= 1u << (kt & 7u);
+      }
+      mout[rank] = (uint8_t)m;
+    }
+    if (j + 1 == n_in) {
+      bout[rank + 1] = n_points;
+      cout[rank + 1] = n_in;
+      *n_out = rank + 1;
+    }
+  }
+}
+
+void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32_t* n_in,
+                  uint32_t cap_in, uint32_t n_points, void* kout, uint32_t* bout, uint32_t* cout,
+                  uint8_t* mout, uint32_t* pout, uint64_t* status, uint32_t* tile_counter,
+                  uint32_t* n_out, hipStream_t s) {
+  const uint32_t grid = div_up(cap_in, kCompTile);
+  if (key64)
+    hipLaunchKernelGGL(k_level<uint64_t>, dim3(grid), dim3(kCompBlock), 0, s, (const uint64_t*)kin,
+                       bin, n_in, n_points, (uint64_t*)kout, bout, cout, mout, pout, status,
+                       tile_counter, n_out);
+  else
+    hipLaunchKernelGGL(k_level<uint32_t>, dim3(grid), dim3(kCompBlock), 0, s, (const uint32_t*)kin,
+                       bin, n_in, n_points, (uint32_t*)kout, bout, cout, mout, pout, status,
+                       tile_counter, n_out);
+}
+
+// ---------------------------------------------------------------------------
+// K8: largest box occupancy of a level (for the cluster-size depth rule,
+// Section 3.1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_max_occupancy(const uint32_t* __restrict__ begin,
+                                                       const uint32_t* __restrict__ n_in_p,
+                                                       uint32_t* __restrict__ out) {
+  const uint32_t n_in = *n_in_p;
+  uint32_t m = 0;
+  for (uint64_t j = blockIdx.x * 256ull + threadIdx.x; j < n_in; j += gridDim.x * 256ull)
+    m = max(m, begin[j + 1] - begin[j]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+void launch_max_occupancy(const uint32_t* begin, const uint32_t* n_in, uint32_t cap,
+                          uint32_t* out, hipStream_t s) {
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 2048));
+  hipLaunchKernelGGL(k_max_occupancy, dim3(grid), dim3(256), 0, s, begin, n_in, out);
+}
+
+}  // namespace fmmds

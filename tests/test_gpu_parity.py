@@ -1,0 +1,181 @@
+"""GPU parity: libfmmds through its C ABI against the CPU oracle.
+
+Bit-exact on every output (all integer tables and lists, FP32 coordinates
+copied bit for bit). Small cases compare every array; the full-size
+workloads (two 2^24-point sets) compare every table array and sampled
+receiver lists against the oracle's per-box definition, plus structure
+properties of the whole lists.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import parity
+from paper_1301_1704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_1704_amd as F
+    if not os.path.exists(F.LIB_PATH):
+        from paper_1301_1704_amd import build
+        build.build()
+    F._lib()
+    return F
+
+
+def _run(F, oracle_lib, src, recv, *, L, kb=64, s=0, lists="full", allocator="pool"):
+    import torch
+    _say(f"case n_src={len(src)} n_recv={None if recv is None else len(recv)} L={L} kb={kb} s={s}")
+    gs = parity.to_gpu(src)
+    gr = None if recv is None else parity.to_gpu(recv)
+    g = F.build(gs, gr, max_level=L, key_bits=kb, cluster_s=s, allocator=allocator)
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleTree(src, recv, key_bits=kb, cluster_s=s, max_level=L,
+                              with_lists=(lists == "full"))
+    parity.compare_tables(g, o, kb)
+    if lists == "full":
+        parity.compare_lists(g, o)
+    else:
+        parity.compare_lists_sampled(g, o)
+    return g, o
+
+
+def test_plain_small_config(F, oracle_lib):
+    """65,536 uniform points shared by sources and receivers, max level 5,
+    32-bit keys: the whole output against the oracle."""
+    c = I.config_plain_small()
+    g, o = _run(F, oracle_lib, c["src"], c["recv"], L=c["max_level"], kb=c["key_bits"])
+    assert g.shared and g.depth == 5
+    g.free()
+
+
+@pytest.mark.parametrize("n_src,n_recv,L", [
+    (1, 1, 2), (2, 3, 2), (4095, 4097, 3), (4096, 2049, 4), (2047, 8193, 5),
+    (40000, 33333, 6), (100003, 65537, 7)])
+def test_uniform_separate_ragged(F, oracle_lib, n_src, n_recv, L):
+    src = I.uniform_points(100 + n_src, n_src)
+    recv = I.uniform_points(200 + n_recv, n_recv)
+    _run(F, oracle_lib, src, recv, L=L)[0].free()
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_nonuniform_depth_rule(F, oracle_lib, kb):
+    """Sphere + clusters with the cluster-size depth rule."""
+    src = I.sphere_cluster_points(31, 30, 60001)
+    recv = I.sphere_cluster_points(32, 30, 50000)
+    for s in (64, 400, 5000):
+        g, o = _run(F, oracle_lib, src, recv, L=9, kb=kb, s=s)
+        g.free()
+
+
+def test_wide_keys(F, oracle_lib):
+    """More than 32 key bits (max level 12, 36 bits): the unpacked sort."""
+    src = I.sphere_cluster_points(41, 40, 30000)
+    recv = I.uniform_points(42, 20000)
+    _run(F, oracle_lib, src, recv, L=12)[0].free()
+
+
+def test_degenerate_inputs(F, oracle_lib):
+    # every point in one box; points on box faces; duplicates; extremes
+    one = np.full((5000, 3), 0.3, dtype=np.float32)
+    _run(F, oracle_lib, one, None, L=6)[0].free()
+    f = np.asarray([0.0, 0.25, 0.5, 0.75, np.nextafter(np.float32(0.5), np.float32(0)),
+                    np.float32(1 - 2 ** -24), -0.0, 1e-45], dtype=np.float32)
+    pts = np.stack(np.meshgrid(f, f, f, indexing="ij"), -1).reshape(-1, 3)
+    pts = np.concatenate([pts, pts[::3]], axis=0)
+    _run(F, oracle_lib, pts, pts[::-1].copy(), L=8)[0].free()
+
+
+def test_key_width_does_not_change_other_outputs(F):
+    import torch
+    src = parity.to_gpu(I.uniform_points(51, 30000))
+    a = F.build(src, None, max_level=7, key_bits=32)
+    b = F.build(src, None, max_level=7, key_bits=64)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.host_perm(0), b.host_perm(0))
+    for l in range(8):
+        assert np.array_equal(a.host_keys(0, l).astype(np.uint64), b.host_keys(0, l))
+        assert np.array_equal(a.host_begin(0, l), b.host_begin(0, l))
+    for l in range(2, 8):
+        for k in (2, 4):
+            for x, y in zip(a.host_list(k, l), b.host_list(k, l)):
+                assert np.array_equal(x, y)
+    a.free()
+    b.free()
+
+
+def test_deterministic_and_allocator_independent(F):
+    import torch
+    src = parity.to_gpu(I.sphere_cluster_points(61, 60, 200000))
+    recv = parity.to_gpu(I.uniform_points(62, 150000))
+    a = F.build(src, recv, max_level=8)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b = F.build(src, recv, max_level=8, allocator="torch")
+    torch.cuda.synchronize()
+    for s in (0, 1):
+        assert np.array_equal(a.host_perm(s), b.host_perm(s))
+        for l in range(9):
+            assert np.array_equal(a.host_begin(s, l), b.host_begin(s, l))
+    for l in range(2, 9):
+        for k in (2, 4):
+            for x, y in zip(a.host_list(k, l), b.host_list(k, l)):
+                assert np.array_equal(x, y)
+    a.free()
+    b.free()
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, 1.0, -1e-7, 2.0])
+def test_range_error(F, bad):
+    import torch
+    p = I.uniform_points(71, 10000)
+    p[7777, 1] = bad
+    with pytest.raises(F.FmmdsError) as e:
+        F.build(parity.to_gpu(p), None, max_level=5)
+    assert e.value.status == F.ERR_RANGE
+    # a valid build afterwards still works
+    t = F.build(parity.to_gpu(I.uniform_points(72, 1000)), None, max_level=4)
+    torch.cuda.synchronize()
+    assert t.n_boxes(0, 0) == 1
+    t.free()
+
+
+def test_list_level_errors(F):
+    t = F.build(parity.to_gpu(I.uniform_points(81, 1000)), None, max_level=4)
+    for bad in (0, 1, 5, 30):
+        with pytest.raises(F.FmmdsError) as e:
+            t.neighbors(bad)
+        assert e.value.status == F.ERR_LEVEL
+    t.free()
+
+
+# --------------------------------------------------------------- full size
+
+@pytest.mark.timeout(900)
+def test_full_uniform_2x2p24_L8(F, oracle_lib):
+    """Two independent 2^24-point uniform sets, max level 8, 64-bit keys: the
+    configuration the benchmark times."""
+    c = I.config_plain_uniform()
+    _run(F, oracle_lib, c["src"], c["recv"], L=8, lists="sampled")[0].free()
+
+
+@pytest.mark.timeout(900)
+def test_full_nonuniform_2x2p24_L10_s64(F, oracle_lib):
+    """Two 2^24-point sphere + cluster sets, max level 10, cluster size 64."""
+    c = I.config_plain_nonuniform()
+    g, o = _run(F, oracle_lib, c["src"], c["recv"], L=10, s=64, lists="sampled")
+    assert g.depth == o.depth
+    g.free()
