@@ -78,7 +78,7 @@ typedef struct fmmds_options {
   uint32_t max_level;  /* finest level considered, in [2, key_bits / 3] */
   uint32_t reserved;   /* must be 0 */
   void* stream;        /* hipStream_t the build is ordered on; NULL = null stream */
-  fmmds_alloc_fn alloc;      /* NULL: stream-ordered hipMallocAsync pool */
+  fmmds_alloc_fn alloc;      /* NULL: the library's caching allocator (see fmmds_trim) */
   fmmds_release_fn release;  /* must be set iff alloc is set */
   void* alloc_ctx;
 } fmmds_options;
@@ -147,6 +147,12 @@ fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint3
  * accepted. Pointers obtained from the tree become invalid. */
 void fmmds_free(fmmds_tree* t);
 
+/* Memory the library allocates itself (opt->alloc == NULL) is cached after
+ * release, per device, and reused by later builds of similar size. This call
+ * synchronizes every device the cache holds memory of and returns all cached
+ * blocks to HIP. Memory of live trees is not affected. */
+void fmmds_trim(void);
+
 /*
  * Diagnostics: per-kernel timing. While enabled, every kernel a build
  * launches is bracketed by HIP events on the build stream; at the end of each
@@ -163,7 +169,10 @@ typedef struct fmmds_kernel_stat {
   double bytes;      /* summed algorithmic bytes */
 } fmmds_kernel_stat;
 
-void fmmds_profile_enable(int on);
+/* on != 0 enables timing; `only` = NULL times every kernel, else only the
+ * kernel of that name (so a timed run carries two events per launch of one
+ * kernel instead of two per launch of every kernel). */
+void fmmds_profile_enable(int on, const char* only);
 void fmmds_profile_reset(void);
 /* Copies up to `cap` entries into `out` (host); returns the number of kernels
  * with statistics. */

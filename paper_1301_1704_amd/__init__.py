@@ -80,7 +80,8 @@ def _lib():
             getattr(L, f).restype = C.c_int
         L.fmmds_free.argtypes = [C.POINTER(TreeStruct)]
         L.fmmds_free.restype = None
-        L.fmmds_profile_enable.argtypes = [C.c_int]
+        L.fmmds_trim.restype = None
+        L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
         L.fmmds_profile_enable.restype = None
         L.fmmds_profile_reset.restype = None
         L.fmmds_profile_read.argtypes = [C.POINTER(KernelStat), _u32]
@@ -98,13 +99,19 @@ def _lib():
 
 def exported_symbols():
     return ["fmmds_build", "fmmds_neighbors", "fmmds_interactions", "fmmds_free",
-            "fmmds_profile_enable", "fmmds_profile_reset", "fmmds_profile_read",
-            "fmmds_status_string"]
+            "fmmds_trim", "fmmds_profile_enable", "fmmds_profile_reset",
+            "fmmds_profile_read", "fmmds_status_string"]
 
 
-def profile_enable(on: bool = True):
-    """Time every kernel of later builds with HIP events on the build stream."""
-    _lib().fmmds_profile_enable(1 if on else 0)
+def trim():
+    """Return the library's cached device memory to HIP."""
+    _lib().fmmds_trim()
+
+
+def profile_enable(on: bool = True, only: str | None = None):
+    """Time kernels of later builds with HIP events on the build stream: every
+    kernel, or only the one named `only`."""
+    _lib().fmmds_profile_enable(1 if on else 0, None if only is None else only.encode())
 
 
 def profile_reset():

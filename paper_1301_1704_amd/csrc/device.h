@@ -111,4 +111,43 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* col, uint64_t stride, uin
   return excl;
 }
 
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// The same chained scan for a single counter, called by all 64 lanes of one
+// wave: lane i inspects tile (t - i), so one round covers 64 predecessors.
+// The nearest predecessor holding an inclusive prefix ends the walk; every
+// tile between it and this one must at least have published its aggregate.
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t* status, uint32_t tile, uint64_t agg) {
+  const uint32_t lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) st_status(status, kStInc | agg);
+    return 0;
+  }
+  if (lane == 0) st_status(status + tile, kStAgg | agg);
+  uint64_t excl = 0;
+  int64_t hi = (int64_t)tile - 1;
+  while (true) {
+    const int64_t t = hi - (int64_t)lane;
+    const uint64_t s = t >= 0 ? ld_status(status + t) : kStInc;
+    const uint64_t f = s >> 62;
+    const uint64_t inc = __ballot(f == 2);
+    const uint64_t not_ready = __ballot(f == 0);
+    const uint32_t first = inc ? (uint32_t)(__ffsll((long long)inc) - 1) : 64u;
+    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+    if (not_ready & need) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += wave_sum_u64(lane <= first ? (s & kStVal) : 0);
+    if (first < 64) break;
+    hi -= 64;
+  }
+  if (lane == 0) st_status(status + tile, kStInc | (excl + agg));
+  return excl;
+}
+
 }  // namespace fmmds

@@ -59,17 +59,18 @@ void launch_max_occupancy(const uint32_t* begin, const uint32_t* n_in, uint32_t 
 
 // ---- lists.hip
 struct ListLevelArgs {
-  uint32_t level;
-  uint32_t n_recv;             // receiver boxes at `level`
-  const void* recv_key;        // level
-  const uint32_t* recv_parent; // level
-  const void* src_key_up;      // level - 1
-  const uint8_t* src_mask_up;  // level - 1
-  const uint32_t* src_child_up;// level - 1
-  const uint32_t* e2_off_up;   // level - 1 (unused when up_all)
+  uint32_t level;               // lists are built for receiver boxes of this level
+  uint32_t n_recv_up;           // receiver boxes at level - 1 (the parents)
+  const void* recv_key_up;      // level - 1 receiver keys
+  const uint8_t* recv_mask_up;  // level - 1 receiver child masks
+  const uint32_t* recv_child_up;// level - 1 receiver first children
+  const void* src_key_up;       // level - 1 source keys
+  const uint8_t* src_mask_up;   // level - 1 source child masks
+  const uint32_t* src_child_up; // level - 1 source first children
+  const uint32_t* e2_off_up;    // E2 lists at level - 1 (unused when up_all)
   const uint32_t* e2_ent_up;
-  uint32_t up_all;             // level - 1 == 1: E2 there is every source box
-  uint32_t n_src_up;           // source boxes at level - 1
+  uint32_t up_all;              // level - 1 == 1: E2 there is every source box
+  uint32_t n_src_up;            // source boxes at level - 1
 };
 void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                        hipStream_t s);

@@ -23,93 +23,190 @@
 
 namespace fmmds {
 
-// Octants with the axis bit clear / set: x is bit 0, y bit 1, z bit 2.
-__device__ __forceinline__ uint32_t axis_adjacent(int d, uint32_t rbit, uint32_t clear,
-                                                  uint32_t set) {
-  return d == 0 ? 0xFFu : (d == 1 ? (rbit ? clear : 0u) : (rbit ? 0u : set));
+// Work mapping: one half-wave (32 lanes) per receiver box p of level l - 1;
+// lane j takes the j-th entry s of E2(p) (at most 27). The lane computes,
+// once for all receiver children of p, the offset of s from p, s's child mask
+// and first child rank, and for each of the 8 child octants q the number of
+// s's children adjacent to a receiver child in octant q. Two packed
+// half-wave scans then give every lane its place in the E2 and E4 list of
+// every receiver child of p at once (E4 places follow from the scan of all
+// children minus the E2 places). For each receiver child r of p, in octant
+// order, the lanes put their entries into a per-half-wave LDS buffer and the
+// half-wave copies r's two lists out contiguously, 128 bytes per store.
+//
+// Offsets per axis come from dilated-integer subtraction on the Morton keys:
+// with only one axis' bits kept in both operands, borrows run through the
+// cleared bits between them, so ((a & M) - (b & M)) & M is the dilated
+// difference of the two coordinates on that axis. Here it is 0, +1 or -1,
+// i.e. 0, the axis' lowest bit, or all of the axis' bits.
+constexpr uint64_t kAxisX = 0x1249249249249249ull;
+constexpr int kHalfBuf = 224;  // E4 at [0, 189), E2 at [kE2At, kE2At + 27)
+constexpr int kE2At = 192;
+
+template <typename A>
+__device__ __forceinline__ int axis_delta(A sk, A pk, A axis_mask, A axis_low) {
+  const A d = (A)((sk & axis_mask) - (pk & axis_mask)) & axis_mask;
+  return d == 0 ? 0 : (d == axis_low ? 1 : -1);
 }
 
-template <typename KeyT, int MODE>  // MODE 0: count, 1: fill
+// Inclusive scan within each 32-lane half of the wave.
+__device__ __forceinline__ uint32_t half_incl_scan(uint32_t v) {
+  const uint32_t j = lane_id() & 31u;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 32);
+    if (j >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// E2 count of octant q from the packed words: octants 0..3 sit in bits
+// 8 + 6q of word a (bits 0..7 hold the count of all children), 4..7 in bits
+// 6(q - 4) of word b.
+__device__ __forceinline__ uint32_t octant_field(uint32_t a, uint32_t b, uint32_t q) {
+  return q < 4 ? (a >> (8 + 6 * q)) & 63u : (b >> (6 * (q - 4))) & 63u;
+}
+
+template <typename KeyT, typename A, int MODE>  // MODE 0: count, 1: fill
 __global__ __launch_bounds__(256) void k_lists(
     ListLevelArgs a, uint32_t* __restrict__ cnt2, uint32_t* __restrict__ cnt4,
     const uint32_t* __restrict__ off2, const uint32_t* __restrict__ off4,
     uint32_t* __restrict__ ent2, uint32_t* __restrict__ ent4) {
-  const uint64_t r = blockIdx.x * 256ull + threadIdx.x;
-  if (r >= a.n_recv) return;
-  const KeyT* __restrict__ rkey = (const KeyT*)a.recv_key;
+  __shared__ uint32_t s_buf[MODE == 1 ? 8 : 1][kHalfBuf];
+  const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
-  const uint64_t rk = (uint64_t)rkey[r];
-  const uint32_t q = (uint32_t)(rk & 7u);
-  const uint64_t pk = rk >> 3;
-  const int px = (int)compact3(pk), py = (int)compact3(pk >> 1), pz = (int)compact3(pk >> 2);
-  const uint32_t p = a.recv_parent[r];
-  uint32_t j0, j1;
+  const uint32_t j = threadIdx.x & 31u, h = threadIdx.x >> 5;
+  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  if (p >= a.n_recv_up) return;  // whole half-wave
+  uint32_t j0, cnt;
   if (a.up_all) {
     j0 = 0;
-    j1 = a.n_src_up;
+    cnt = a.n_src_up;
   } else {
     j0 = a.e2_off_up[p];
-    j1 = a.e2_off_up[p + 1];
+    cnt = a.e2_off_up[p + 1] - j0;
   }
-  uint32_t c2 = 0, c4 = 0;
-  uint32_t o2 = 0, o4 = 0;
-  if (MODE == 1) {
-    o2 = off2[r];
-    o4 = off4[r];
-  }
-  for (uint32_t j = j0; j < j1; ++j) {
-    const uint32_t s = a.up_all ? j : a.e2_ent_up[j];
-    const uint64_t sk = (uint64_t)skey[s];
-    const int dx = (int)compact3(sk) - px;
-    const int dy = (int)compact3(sk >> 1) - py;
-    const int dz = (int)compact3(sk >> 2) - pz;
-    const uint32_t m = a.src_mask_up[s];
-    const uint32_t adj = axis_adjacent(dx, q & 1u, 0x55u, 0xAAu) &
-                         axis_adjacent(dy, (q >> 1) & 1u, 0x33u, 0xCCu) &
-                         axis_adjacent(dz, (q >> 2) & 1u, 0x0Fu, 0xF0u);
-    if (MODE == 0) {
-      c2 += __popc(m & adj);
-      c4 += __popc(m & ~adj);
-    } else {
-      uint32_t rank = a.src_child_up[s];
-      uint32_t mm = m;
-      while (mm) {
-        const uint32_t bit = mm & (0u - mm);
-        if (adj & bit) ent2[o2++] = rank;
-        else ent4[o4++] = rank;
-        ++rank;
-        mm ^= bit;
-      }
+  const uint32_t rmask = a.recv_mask_up[p];
+  const uint32_t rfirst = a.recv_child_up[p];
+  uint32_t m = 0, cb = 0, wa = 0, wb = 0;
+  uint32_t ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
+  if (j < cnt) {
+    const uint32_t s = a.up_all ? j : a.e2_ent_up[j0 + j];
+    const A sk = (A)skey[s], pk = (A)pkey[p];
+    const A X = (A)kAxisX;
+    const int dx = axis_delta<A>(sk, pk, X, (A)1);
+    const int dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
+    const int dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
+    m = a.src_mask_up[s];
+    if (MODE == 1) cb = a.src_child_up[s];
+    // Children of s adjacent to a receiver child whose axis bit is 0 / 1:
+    // offset 0: all; +1: child bit 0 and receiver bit 1; -1: child bit 1 and
+    // receiver bit 0. Octants with the x / y / z bit clear: 0x55 / 0x33 / 0x0F.
+    ax0 = dx == 0 ? 0xFFu : (dx < 0 ? 0xAAu : 0u);
+    ax1 = dx == 0 ? 0xFFu : (dx > 0 ? 0x55u : 0u);
+    ay0 = dy == 0 ? 0xFFu : (dy < 0 ? 0xCCu : 0u);
+    ay1 = dy == 0 ? 0xFFu : (dy > 0 ? 0x33u : 0u);
+    az0 = dz == 0 ? 0xFFu : (dz < 0 ? 0xF0u : 0u);
+    az1 = dz == 0 ? 0xFFu : (dz > 0 ? 0x0Fu : 0u);
+    wa = (uint32_t)__popc(m);
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+      const uint32_t adj = ((q & 1u) ? ax1 : ax0) & ((q & 2u) ? ay1 : ay0) & ((q & 4u) ? az1 : az0);
+      const uint32_t c2 = __popc(m & adj);
+      if (q < 4) wa |= c2 << (8 + 6 * q);
+      else wb |= c2 << (6 * (q - 4));
     }
   }
-  if (MODE == 0) {
-    cnt2[r] = c2;
-    cnt4[r] = c4;
+  // Each field's sum over the half-wave stays in range: all children <= 216,
+  // E2 of one octant <= 27.
+  const uint32_t ia = half_incl_scan(wa), ib = half_incl_scan(wb);
+  const uint32_t ea = ia - wa, eb = ib - wb;
+  const uint32_t ta = __shfl(ia, 31, 32), tb = __shfl(ib, 31, 32);
+  // Offsets of p's receiver children, loaded up front (lane k holds child k)
+  // so that no load sits inside the loop below: on this GPU a wait for a load
+  // also waits for every store issued before it.
+  const uint32_t nchild = __popc(rmask);
+  uint32_t my_o2 = 0, my_o4 = 0;
+  if (MODE == 1 && j < nchild) {
+    my_o2 = off2[rfirst + j];
+    my_o4 = off4[rfirst + j];
   }
+  uint32_t* buf = s_buf[MODE == 1 ? h : 0];
+  uint32_t k = 0;
+  uint32_t qm = rmask;
+#pragma unroll 1
+  while (qm) {
+    const uint32_t q = __builtin_ctz(qm);
+    qm &= qm - 1;
+    const uint32_t n2 = octant_field(ta, tb, q), n4 = (ta & 0xFFu) - n2;
+    if (MODE == 0) {
+      if (j == 0) {
+        cnt2[rfirst + k] = n2;
+        cnt4[rfirst + k] = n4;
+      }
+    } else {
+      const uint32_t o2 = __shfl(my_o2, k, 32), o4 = __shfl(my_o4, k, 32);
+      const uint32_t adj = ((q & 1u) ? ax1 : ax0) & ((q & 2u) ? ay1 : ay0) & ((q & 4u) ? az1 : az0);
+      const uint32_t b2 = kE2At + octant_field(ea, eb, q);
+      const uint32_t b4 = (ea & 0xFFu) - octant_field(ea, eb, q);
+      const uint32_t e2b = m & adj, e4b = m & ~adj;
+      // Child octant o of s: rank cb + (children of s below o); it goes to E2
+      // after the E2 children below it, else to E4 after the E4 ones below it.
+#pragma unroll
+      for (uint32_t o = 0; o < 8; ++o) {
+        const uint32_t below = (1u << o) - 1u;
+        if (m & (1u << o)) {
+          const uint32_t pos = (adj & (1u << o)) ? b2 + __popc(e2b & below)
+                                                 : b4 + __popc(e4b & below);
+          buf[pos] = cb + __popc(m & below);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      uint32_t v4[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const uint32_t idx = j + 32u * i;
+        v4[i] = idx < n4 ? buf[idx] : 0u;
+      }
+      const uint32_t v2 = j < n2 ? buf[kE2At + j] : 0u;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const uint32_t idx = j + 32u * i;
+        if (idx < n4) ent4[(uint64_t)o4 + idx] = v4[i];
+      }
+      if (j < n2) ent2[(uint64_t)o2 + j] = v2;
+      __builtin_amdgcn_wave_barrier();
+    }
+    ++k;
+  }
+}
+
+template <int MODE>
+void launch_lists(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
+                  const uint32_t* off2, const uint32_t* off4, uint32_t* ent2, uint32_t* ent4,
+                  hipStream_t s) {
+  if (a.n_recv_up == 0) return;
+  const uint32_t grid = div_up(a.n_recv_up, 8);
+  const bool narrow = 3 * (a.level - 1) <= 32;  // parent-level keys fit 32 bits
+  if (key64 && narrow)
+    hipLaunchKernelGGL((k_lists<uint64_t, uint32_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4, off2, off4, ent2, ent4);
+  else if (key64)
+    hipLaunchKernelGGL((k_lists<uint64_t, uint64_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4, off2, off4, ent2, ent4);
+  else
+    hipLaunchKernelGGL((k_lists<uint32_t, uint32_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4, off2, off4, ent2, ent4);
 }
 
 void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                        hipStream_t s) {
-  if (a.n_recv == 0) return;
-  const uint32_t grid = div_up(a.n_recv, 256);
-  if (key64)
-    hipLaunchKernelGGL((k_lists<uint64_t, 0>), dim3(grid), dim3(256), 0, s, a, cnt2, cnt4, nullptr,
-                       nullptr, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_lists<uint32_t, 0>), dim3(grid), dim3(256), 0, s, a, cnt2, cnt4, nullptr,
-                       nullptr, nullptr, nullptr);
+  launch_lists<0>(key64, a, cnt2, cnt4, nullptr, nullptr, nullptr, nullptr, s);
 }
 
 void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
                       const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s) {
-  if (a.n_recv == 0) return;
-  const uint32_t grid = div_up(a.n_recv, 256);
-  if (key64)
-    hipLaunchKernelGGL((k_lists<uint64_t, 1>), dim3(grid), dim3(256), 0, s, a, nullptr, nullptr,
-                       off2, off4, ent2, ent4);
-  else
-    hipLaunchKernelGGL((k_lists<uint32_t, 1>), dim3(grid), dim3(256), 0, s, a, nullptr, nullptr,
-                       off2, off4, ent2, ent4);
+  launch_lists<1>(key64, a, nullptr, nullptr, off2, off4, ent2, ent4, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,7 +242,10 @@ __global__ __launch_bounds__(kCompBlock) void k_scan_counts(
     if (i < w) wpre += s_w[i];
     ttot += s_w[i];
   }
-  if (tid == 0) s_excl = lookback(status, 1, tile, ttot);
+  if (w == 0) {
+    const uint64_t ex = lookback_wave(status, tile, ttot);
+    if (lane == 0) s_excl = ex;
+  }
   __syncthreads();
   uint64_t pre = s_excl + wpre + inc - sum;
   bool ovf = false;

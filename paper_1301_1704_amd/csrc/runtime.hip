@@ -13,6 +13,7 @@
 #include <atomic>
 #include <mutex>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -33,7 +34,101 @@ inline void ck_launch() { ck(hipGetLastError()); }
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Device memory through the caller's allocator, or the stream-ordered pool.
+// ---------------------------------------------------------------------------
+// Caching device allocator. Builds allocate and release the same sizes over
+// and over (rebuilds of moving particles, benchmark loops), and a round trip
+// through the HIP allocator costs tens to hundreds of microseconds. Released
+// blocks stay cached per device and are handed out again for a request of at
+// most the block's size and at least 7/8 of it. A block released on stream S
+// may still be used by work queued on S: it is reused at once on S (stream
+// order protects it); another stream first waits on an event recorded on S at
+// release time. fmmds_trim returns every cached block to HIP.
+// ---------------------------------------------------------------------------
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipStream_t stream;
+  hipEvent_t ready;  // recorded on `stream` at release
+};
+std::mutex g_cache_mu;
+std::map<int, std::multimap<size_t, CachedBlock>> g_cache;  // device -> size -> block
+std::map<void*, size_t> g_live;                              // pointer -> bytes
+
+size_t cache_round(size_t bytes) {
+  if (bytes <= (1u << 20)) return round_up(bytes, 4096);
+  return round_up(bytes, 2u << 20);
+}
+
+void* cache_alloc(size_t bytes, hipStream_t stream) {
+  int dev = 0;
+  ck(hipGetDevice(&dev));
+  bytes = cache_round(bytes);
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto& m = g_cache[dev];
+    auto best = m.end();
+    for (auto it = m.lower_bound(bytes); it != m.end() && it->first - bytes <= it->first / 8;
+         ++it) {
+      if (it->second.stream == stream) {
+        best = it;
+        break;
+      }
+      if (best == m.end()) best = it;
+    }
+    if (best != m.end()) {
+      CachedBlock b = best->second;
+      m.erase(best);
+      if (b.stream != stream) ck(hipStreamWaitEvent(stream, b.ready, 0));
+      (void)hipEventDestroy(b.ready);
+      g_live[b.p] = b.bytes;
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    // Out of memory: give the cache back to HIP and try once more.
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto& m = g_cache[dev];
+    if (!m.empty()) {
+      (void)hipDeviceSynchronize();
+      for (auto& kv : m) {
+        (void)hipFree(kv.second.p);
+        (void)hipEventDestroy(kv.second.ready);
+      }
+      m.clear();
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+      }
+    }
+    if (!p) return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  g_live[p] = bytes;
+  return p;
+}
+
+void cache_release(void* p, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamSynchronize(stream);
+    ev = nullptr;
+    (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  }
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  g_cache[dev].insert({it->second, CachedBlock{p, it->second, stream, ev}});
+  g_live.erase(it);
+}
+
+// Device memory through the caller's allocator, or the library's cache.
 struct Allocator {
   fmmds_alloc_fn alloc = nullptr;
   fmmds_release_fn release = nullptr;
@@ -42,13 +137,7 @@ struct Allocator {
 
   void* get(size_t bytes) {
     bytes = round_up(std::max<size_t>(bytes, 1), 256);
-    void* p = nullptr;
-    if (alloc) {
-      p = alloc(ctx, bytes, (void*)stream);
-    } else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-    }
+    void* p = alloc ? alloc(ctx, bytes, (void*)stream) : cache_alloc(bytes, stream);
     if (!p) throw Fail{FMMDS_ERR_NOMEM};
     return p;
   }
@@ -56,7 +145,7 @@ struct Allocator {
     if (!p) return;
     bytes = round_up(std::max<size_t>(bytes, 1), 256);
     if (release) release(ctx, p, bytes, (void*)stream);
-    else (void)hipFreeAsync(p, stream);
+    else cache_release(p, stream);
   }
 };
 
@@ -130,21 +219,6 @@ struct TreeImpl {
   uint32_t n_recv_boxes[kMaxLevel + 1] = {};
 };
 
-bool g_pool_configured[64] = {};
-
-void configure_default_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  if (g_pool_configured[dev]) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = ~0ull;  // keep freed blocks cached for the next build
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  (void)hipGetLastError();
-  g_pool_configured[dev] = true;
-}
-
 uint32_t level_cap(uint32_t n, uint32_t l) {
   const uint64_t boxes = 1ull << (3 * l);
   return (uint32_t)std::min<uint64_t>(n, boxes);
@@ -187,6 +261,7 @@ struct ClassStat {
   double ms = 0, bytes = 0;
 };
 std::atomic<int> g_prof_on{0};
+std::atomic<int> g_prof_only{-1};  // -1: every kernel class
 std::mutex g_prof_mu;
 ClassStat g_prof[K_NCLASS];
 std::vector<hipEvent_t> g_events;  // reusable, guarded by g_prof_mu
@@ -215,9 +290,10 @@ struct Prof {
     ck(hipEventCreate(&e));
     return e;
   }
+  int only = -1;
   template <typename F>
   void run(int cls, double bytes, F&& f, int set = -1, int level = -1) {
-    if (!on) {
+    if (!on || (only >= 0 && cls != only)) {
       f();
       ck_launch();
       return;
@@ -295,9 +371,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
   fmmds_status result = FMMDS_OK;
   Prof P;
   P.on = g_prof_on.load() != 0;
+  P.only = g_prof_only.load();
   P.s = st;
   try {
-    if (!opt->alloc) configure_default_pool();
     SetBufs sets[2];
     sets[0].xyz = src_xyz;
     sets[0].n = n_src;
@@ -458,9 +534,10 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const uint32_t nr = nb[rs][l];
       ListLevelArgs a{};
       a.level = l;
-      a.n_recv = nr;
-      a.recv_key = sets[rs].lv[l].key;
-      a.recv_parent = sets[rs].lv[l].parent;
+      a.n_recv_up = nb[rs][l - 1];
+      a.recv_key_up = sets[rs].lv[l - 1].key;
+      a.recv_mask_up = sets[rs].lv[l - 1].mask;
+      a.recv_child_up = sets[rs].lv[l - 1].child;
       a.src_key_up = sets[0].lv[l - 1].key;
       a.src_mask_up = sets[0].lv[l - 1].mask;
       a.src_child_up = sets[0].lv[l - 1].child;
@@ -474,7 +551,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       // receiver key + parent in, two counts out; the parent lists and the
       // parent-level source keys, masks and first children read once
       const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
-      const double side = (double)nr * (ksz + 4) + e2up * 4 + (double)nb[0][l - 1] * (ksz + 5);
+      const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
+                          (double)nb[0][l - 1] * (ksz + 1 + 4);
       P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + nr, st); });
       for (int k = 0; k < 2; ++k) {
         LB.off[k] = impl->outs.get<uint32_t>((size_t)nr + 1);
@@ -599,7 +677,34 @@ void fmmds_free(fmmds_tree* t) {
   delete t;
 }
 
-void fmmds_profile_enable(int on) { fmmds::g_prof_on.store(on ? 1 : 0); }
+void fmmds_trim(void) {
+  std::lock_guard<std::mutex> g(fmmds::g_cache_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  bool any = false;
+  for (auto& d : fmmds::g_cache) any |= !d.second.empty();
+  if (!any) return;
+  (void)hipDeviceSynchronize();
+  for (auto& d : fmmds::g_cache) {
+    (void)hipSetDevice(d.first);
+    for (auto& kv : d.second) {
+      (void)hipFree(kv.second.p);
+      (void)hipEventDestroy(kv.second.ready);
+    }
+    d.second.clear();
+  }
+  (void)hipSetDevice(dev);
+}
+
+void fmmds_profile_enable(int on, const char* only) {
+  int cls = -1;
+  if (only) {
+    for (int k = 0; k < fmmds::K_NCLASS; ++k)
+      if (std::strcmp(only, fmmds::kClassName[k]) == 0) cls = k;
+  }
+  fmmds::g_prof_only.store(cls);
+  fmmds::g_prof_on.store(on ? 1 : 0);
+}
 
 void fmmds_profile_reset(void) {
   std::lock_guard<std::mutex> g(fmmds::g_prof_mu);

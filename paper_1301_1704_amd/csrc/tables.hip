@@ -31,7 +31,8 @@ __device__ __forceinline__ uint64_t tile_flags_prefix(uint32_t* s_cnt, uint64_t*
     const uint32_t inc = wave_incl_scan(c);
     if (lane < kCompItems * kCompWaves) s_cnt[lane] = inc - c;
     const uint32_t total = __shfl(inc, 63, 64);
-    if (lane == 0) *s_excl = lookback(status, 1, tile, total);
+    const uint64_t ex = lookback_wave(status, tile, total);
+    if (lane == 0) *s_excl = ex;
   }
   __syncthreads();
   return *s_excl;

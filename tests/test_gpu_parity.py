@@ -179,3 +179,23 @@ def test_full_nonuniform_2x2p24_L10_s64(F, oracle_lib):
     g, o = _run(F, oracle_lib, c["src"], c["recv"], L=10, s=64, lists="sampled")
     assert g.depth == o.depth
     g.free()
+
+
+def test_cache_reuse_and_trim(F):
+    """Builds reuse cached device memory; after fmmds_trim they still work and
+    give the same result."""
+    import torch
+    src = parity.to_gpu(I.uniform_points(91, 50000))
+    a = F.build(src, None, max_level=6)
+    ref = [a.host_list(k, 6) for k in (2, 4)]
+    a.free()
+    for _ in range(3):
+        b = F.build(src, None, max_level=6)
+        b.free()
+    F.trim()
+    c = F.build(src, None, max_level=6)
+    torch.cuda.synchronize()
+    for k, (o, e) in zip((2, 4), ref):
+        co, ce = c.host_list(k, 6)
+        assert np.array_equal(co, o) and np.array_equal(ce, e)
+    c.free()
