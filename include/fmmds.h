@@ -7,16 +7,16 @@
  * Constructing Data Structures for Fast Multipole Methods" (arXiv 1301.1704):
  *
  *   - the Morton index of every point's box at the finest level and the
- *     points reordered by it (Section 3.1, Algorithm 1);
+ *     points reordered by it (Section 2.1, Algorithm 1);
  *   - per level, the Morton indices of the nonempty boxes and their bookmarks,
- *     i.e. the first reordered point of each box (Section 3.2, Algorithm 3);
+ *     i.e. the first reordered point of each box (Section 2.2; Algorithm 3 in Section 2.3);
  *   - per level, parent and children links (the parent/children queries of
- *     Section 3.4; the parent index is the child index shifted right by one
- *     level, Section 4.2);
+ *     Section 2.4; the parent index is the child index shifted right by one
+ *     level, Section 3.2);
  *   - per level 2..depth, for every nonempty receiver box, the E2 neighbor
- *     list (at most 27 nonempty source boxes, Section 2.4 item 2 and
+ *     list (at most 27 nonempty source boxes, Section 1.4 item 2 and
  *     Algorithm 4) and the E4 interaction (M2L) list (at most 189 nonempty
- *     source boxes, Section 2.4 item 4).
+ *     source boxes, Section 1.4 item 4).
  *
  * Conventions (the paper leaves these open):
  *   - level l has 8^l boxes; a box has integer coordinates (cx, cy, cz) in
@@ -32,7 +32,7 @@
  *     index into that level's source tables), in ascending order.
  *   - depth: if cluster_s == 0 the depth is max_level. Otherwise it is the
  *     smallest level l in [2, max_level] at which no source box and no
- *     receiver box holds more than cluster_s points (Section 3.1: the cluster
+ *     receiver box holds more than cluster_s points (Section 2.1: the cluster
  *     size fixes the finest level), or max_level if no level qualifies.
  *
  * Memory: every pointer passed in or returned is a DEVICE pointer on the
@@ -111,7 +111,7 @@ typedef struct fmmds_tree {
 
 /*
  * Build all tables and lists (Algorithm 5 of the paper, with the lists of
- * Section 3.2 at every level 2..depth).
+ * Section 2.2 at every level 2..depth).
  *   src_xyz:  device, 3 * n_src FP32 values, (x, y, z) per point.
  *   recv_xyz: device, 3 * n_recv FP32 values, or NULL: receivers are the
  *             sources and n_recv is ignored.
@@ -125,7 +125,7 @@ fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv
 
 /*
  * E2 neighbor list of every nonempty receiver box at `level` in [2, depth]
- * (Section 3.2, NeighborBookmark / NeighborList), as CSR:
+ * (Section 2.2, NeighborBookmark / NeighborList), as CSR:
  *   *offsets: device, *n_recv_boxes + 1 entries; box j's list is
  *             entries[offsets[j] .. offsets[j+1]).
  *   *entries: device, *n_entries source ranks at `level`, ascending per box.
@@ -137,7 +137,7 @@ fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t
 
 /*
  * E4 interaction (M2L) list of every nonempty receiver box at `level` in
- * [2, depth] (Section 2.4 item 4), same CSR layout as fmmds_neighbors.
+ * [2, depth] (Section 1.4 item 4), same CSR layout as fmmds_neighbors.
  */
 fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
                                 const uint32_t** entries, uint32_t* n_recv_boxes,

@@ -4,22 +4,22 @@
  * Plain single-threaded CPU build of the FMM data structures, written from the
  * definitions of Hu, Gumerov and Duraiswami (arXiv 1301.1704):
  *   - boxes of an octree over the unit cube, Morton index n = 0..8^l - 1 at
- *     level l (Section 2.4);
+ *     level l (Section 1.4);
  *   - points reordered by the Morton index of their finest-level box
- *     (Section 3.1, the Fixed-Grid-Method pseudo-sort, Algorithm 1);
+ *     (Section 2.1, the Fixed-Grid-Method pseudo-sort, Algorithm 1);
  *   - bookmark (first point of each nonempty box) and nonempty-box index
- *     arrays (Section 3.2, Algorithm 3);
- *   - parent and children relations (Section 3.4; the parent is the Morton
- *     index shifted right by one level, Section 4.2);
+ *     arrays (Section 2.2; Algorithm 3 in Section 2.3);
+ *   - parent and children relations (Section 2.4; the parent is the Morton
+ *     index shifted right by one level, Section 3.2);
  *   - E2 neighbor lists and E4 interaction lists of nonempty source boxes per
- *     nonempty receiver box (Section 2.4, Section 3.2, Algorithm 4), as
+ *     nonempty receiver box (Section 1.4, Section 2.2, Algorithm 4), as
  *     ranks among the nonempty source boxes of that level.
  *
  * Nothing here is blocked, fused or reordered for speed: every table and list
  * is computed straight from its definition. Where the paper leaves a choice
  * open this file takes these readings:
  *   - order of points inside a box: ascending original index (the paper's
- *     pseudo-sort leaves it to run-time memory order, Section 3.1);
+ *     pseudo-sort leaves it to run-time memory order, Section 2.1);
  *   - interleave: bit b of the x, y, z box coordinates goes to key bit 3b,
  *     3b+1, 3b+2 (the paper fixes no bit order; its one printed 2-D example
  *     refers to a missing figure);
@@ -72,7 +72,7 @@ struct oref_tree {
 
 namespace {
 
-// Section 2.4: the box of a point at level L has integer coordinates
+// Section 1.4: the box of a point at level L has integer coordinates
 // floor(x * 2^L) per axis. Scaling an FP32 value by 2^L is exact, so this is
 // the exact floor of the real product.
 inline uint32_t quantize(float x, uint32_t L) {
@@ -206,7 +206,7 @@ inline int64_t iabs(int64_t v) { return v < 0 ? -v : v; }
 
 // E2(r): nonempty source boxes s at the level with max_d |c_s - c_r| <= 1.
 // E4(r): nonempty source boxes s with max_d |c_s - c_r| >= 2 whose parent is
-// within max_d |p_s - p_r| <= 1 of the receiver's parent (Section 2.4,
+// within max_d |p_s - p_r| <= 1 of the receiver's parent (Section 1.4,
 // E4(n, l) = E2(parent(n), l - 1) minus E2(n, l), taken over boxes).
 // Entries sorted ascending.
 void box_list(const Lookup& src, int kind, uint64_t recv_key, uint32_t l,

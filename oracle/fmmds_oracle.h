@@ -9,12 +9,12 @@
  * header or constant with the GPU library.
  *
  * All pointers are host pointers. Coordinates are FP32 xyz triples (array of
- * structs) in the half-open unit cube [0, 1)^3 (Section 2.4 assumes the
+ * structs) in the half-open unit cube [0, 1)^3 (Section 1.4 assumes the
  * points are already scaled into the unit cube).
  *
  * Set index: 0 = sources, 1 = receivers. List kind: 2 = E2 (neighbor list,
- * Section 2.4 item 2 and Section 3.2), 4 = E4 (M2L interaction list,
- * Section 2.4 item 4).
+ * Section 1.4 item 2 and Section 2.2), 4 = E4 (M2L interaction list,
+ * Section 1.4 item 4).
  */
 #ifndef FMMDS_ORACLE_H
 #define FMMDS_ORACLE_H

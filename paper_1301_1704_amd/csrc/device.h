@@ -6,8 +6,8 @@
 namespace fmmds {
 
 // ---------------------------------------------------------------------------
-// Morton index arithmetic (Section 2.4: bit b of the box coordinates x, y, z
-// sits at bit 3b, 3b+1, 3b+2 of the index; Section 3.4: interleave and
+// Morton index arithmetic (Section 1.4: bit b of the box coordinates x, y, z
+// sits at bit 3b, 3b+1, 3b+2 of the index; Section 2.4: interleave and
 // deinterleave). Magic-mask bit spreading, 21 bits per axis.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {

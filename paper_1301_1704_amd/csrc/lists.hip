@@ -1,10 +1,10 @@
 // E2 neighbor lists and E4 (M2L) interaction lists per level.
 //
-// Definitions (Section 2.4): for a receiver box r at level l, E2(r) holds the
+// Definitions (Section 1.4): for a receiver box r at level l, E2(r) holds the
 // nonempty source boxes within one box of r in every coordinate (r included);
 // E4(r) holds the nonempty source boxes that are children of boxes in
 // E2(parent(r)) at level l - 1 but are not in E2(r). The paper enumerates the
-// candidate boxes from de-interleaved coordinates (Section 3.3) and looks them
+// candidate boxes from de-interleaved coordinates (Section 2.3) and looks them
 // up in a dense per-box rank array (Algorithm 4).
 //
 // Here the candidates come from the parent level's E2 list: the children of

@@ -2,7 +2,7 @@
 //
 // The paper reorders points by the Morton index of their finest-level box
 // with a histogram pseudo-sort whose order inside a box depends on atomic
-// timing (Section 3.1, Algorithm 1). This library needs a deterministic order,
+// timing (Section 2.1, Algorithm 1). This library needs a deterministic order,
 // so it sorts (key, original index) pairs stably: an LSD radix sort with 8-bit
 // digits, one single-pass "chained scan" kernel per digit.
 #include "device.h"
@@ -28,7 +28,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// K1: Morton key of every point (Section 2.4 box index, Section 3.4
+// K1: Morton key of every point (Section 1.4 box index, Section 2.4
 // interleave) plus the digit histograms of every sort pass.
 //
 // A point (x, y, z) is in the box floor(x * 2^L) per axis; x * 2^L is exact in

@@ -1,13 +1,13 @@
 // Nonempty-box tables: leaf boundary detection plus stream compaction, and the
 // coarser levels, parents, children and child masks.
 //
-// The paper scans a dense histogram of all 8^lmax boxes (Section 3.2,
+// The paper scans a dense histogram of all 8^lmax boxes (Section 2.3,
 // Algorithm 3), which costs memory and time in the number of boxes. Here the
 // sorted keys already group the points by box, so a box starts wherever the
 // key differs from the previous one (adjacent difference) and the starts are
 // compacted with a single-pass scan: the cost follows the nonempty boxes only.
 // Coarser levels repeat this on the previous level's keys shifted right by 3
-// (the parent of a box is its Morton index shifted by one level, Section 4.2).
+// (the parent of a box is its Morton index shifted by one level, Section 3.2).
 #include "device.h"
 #include "internal.h"
 
@@ -204,7 +204,7 @@ void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32
 
 // ---------------------------------------------------------------------------
 // K8: largest box occupancy of a level (for the cluster-size depth rule,
-// Section 3.1).
+// Section 2.1).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_max_occupancy(const uint32_t* __restrict__ begin,
                                                        const uint32_t* __restrict__ n_in_p,

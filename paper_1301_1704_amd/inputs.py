@@ -11,11 +11,11 @@ computed in wrapping uint64 numpy arithmetic, so a stream is counter-based
 and any slice of it can be drawn independently.
 
 Workloads follow the paper's synthetic distributions: uniform points in the
-unit cube (Section 5.1, Table "dsTime") and points on a sphere surface
-(Section 5.1, sphere experiment), plus Gaussian clusters for the nonuniform,
+unit cube (Section 4.1, Table "dsTime") and points on a sphere surface
+(Section 4.1, sphere experiment), plus Gaussian clusters for the nonuniform,
 batched and serving workloads. All coordinates are clamped into
 [0, 1 - 2^-24], which is exactly representable in FP32, so every point lies
-in the half-open unit cube the paper assumes (Section 2.4).
+in the half-open unit cube the paper assumes (Section 1.4).
 """
 from __future__ import annotations
 

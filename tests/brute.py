@@ -8,7 +8,7 @@ than the oracle takes:
     a box inside its parent is its coordinates mod 2), most significant digit
     first, rather than by interleaving the bits of the finest coordinates;
   - lists come from enumerating every (receiver box, source box) pair and
-    testing the distance conditions on coordinates (Section 2.4 E2, E4).
+    testing the distance conditions on coordinates (Section 1.4 E2, E4).
 Only for inputs of a few hundred points.
 """
 from __future__ import annotations

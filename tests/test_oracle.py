@@ -3,7 +3,7 @@
 None of these tests re-runs the oracle's own formulas: expected values come
 from exact rational arithmetic and pair enumeration (tests/brute.py), closed
 forms on the full grid, a hand-worked example, and invariants that any correct
-build satisfies (arXiv 1301.1704, Section 2.4 and Section 3).
+build satisfies (arXiv 1301.1704, Section 1.4 and Section 2).
 """
 import numpy as np
 import pytest
@@ -225,7 +225,7 @@ def test_partition_of_sources(oracle_lib, name, src, recv, L):
     """For every receiver leaf b, the near list E2(b) at the finest level and
     the interaction lists E4 of b's ancestors at levels 2..D cover every
     source point exactly once (the near/far split of Eq. (2) done
-    hierarchically, Section 2.4)."""
+    hierarchically, Section 1.4)."""
     t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
     D = t.depth
     N = src.shape[0]
