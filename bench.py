@@ -91,7 +91,7 @@ def main():
     import paper_1301_1704_amd as F
 
     if not os.path.exists(F.LIB_PATH):
-        from paper_1301_1704_amd import build as hb
+        from paper_1301_1704_amd import _compile as hb
         hb.build()
     c = workload(args.workload)
     log(f"workload {c['name']}: generating inputs")

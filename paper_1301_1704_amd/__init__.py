@@ -68,7 +68,7 @@ def _lib():
     if _LIB is None:
         import torch  # binds the HIP runtime first (see module docstring)
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1301_1704_amd/build.py "
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1301_1704_amd/_compile.py "
                                "(or __graft_entry__.build())")
         L = C.CDLL(LIB_PATH)
         L.fmmds_build.argtypes = [_vp, _u32, _vp, _u32, C.POINTER(Options),

@@ -22,8 +22,8 @@ def declared_functions():
 def lib():
     import paper_1301_1704_amd as F
     if not os.path.exists(F.LIB_PATH):
-        from paper_1301_1704_amd import build
-        build.build()
+        from paper_1301_1704_amd import _compile
+        _compile.build()
     return F._lib()
 
 

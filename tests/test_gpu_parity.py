@@ -30,8 +30,8 @@ def F():
         pytest.skip("no GPU")
     import paper_1301_1704_amd as F
     if not os.path.exists(F.LIB_PATH):
-        from paper_1301_1704_amd import build
-        build.build()
+        from paper_1301_1704_amd import _compile
+        _compile.build()
     F._lib()
     return F
 
