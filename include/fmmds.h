@@ -147,6 +147,45 @@ fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint3
  * accepted. Pointers obtained from the tree become invalid. */
 void fmmds_free(fmmds_tree* t);
 
+/*
+ * Batched form: many independent point sets built by one launch sequence.
+ * Each set is built as fmmds_build would build it with its points as both
+ * sources and receivers, max_level = levels[i], cluster_s = 0 and 64-bit
+ * keys; all of its outputs (ranks, bookmarks, permutation, list offsets and
+ * entries) are local to the set. Not from the paper: it serves the dynamic
+ * problems the paper motivates (Section 1, Eq. (2)), where every time step
+ * rebuilds the structures of many particle systems.
+ *
+ * fmmds_batch_create plans one batch shape and allocates every buffer for
+ * the worst case of that shape (no host synchronization is needed later):
+ *   set_offsets: host, n_sets + 1 point offsets, set_offsets[0] = 0, strictly
+ *                increasing (no empty set), total < 2^32 - 1.
+ *   levels:      host, n_sets max levels in [2, 21].
+ *   opt:         host; key_bits must be 64, cluster_s 0; stream and allocator
+ *                as for fmmds_build.
+ * fmmds_batch_launch enqueues a build of the concatenated coordinates `xyz`
+ * (device, 3 * total FP32, set i at points set_offsets[i] ..) on the batch's
+ * stream and returns at once. With capture != 0 the first launch records the
+ * kernel sequence into a HIP graph and later launches replay it (the input
+ * pointer must then stay the same). Before the first graph capture the sort
+ * tile size is chosen by timing the candidates (autotuning) on this input.
+ * fmmds_batch_wait waits for the launch, checks its status (FMMDS_ERR_RANGE,
+ * FMMDS_ERR_OVERFLOW) and fills the per-set views that fmmds_batch_tree
+ * returns; the views stay valid until the next launch or fmmds_batch_free, and
+ * fmmds_neighbors / fmmds_interactions accept them. fmmds_free ignores them.
+ * A batch is used by one host thread at a time.
+ */
+typedef struct fmmds_batch fmmds_batch;
+
+fmmds_status fmmds_batch_create(const uint64_t* set_offsets, const uint8_t* levels,
+                                uint32_t n_sets, const fmmds_options* opt, fmmds_batch** out);
+fmmds_status fmmds_batch_launch(fmmds_batch* b, const float* xyz, int capture);
+fmmds_status fmmds_batch_wait(fmmds_batch* b);
+const fmmds_tree* fmmds_batch_tree(const fmmds_batch* b, uint32_t set);
+/* Sort tile size (elements per thread: 8, 12 or 16) the batch uses. */
+uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
+void fmmds_batch_free(fmmds_batch* b);
+
 /* Memory the library allocates itself (opt->alloc == NULL) is cached after
  * release, per device, and reused by later builds of similar size. This call
  * synchronizes every device the cache holds memory of and returns all cached

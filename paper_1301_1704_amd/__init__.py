@@ -81,6 +81,18 @@ def _lib():
         L.fmmds_free.argtypes = [C.POINTER(TreeStruct)]
         L.fmmds_free.restype = None
         L.fmmds_trim.restype = None
+        L.fmmds_batch_create.argtypes = [_vp, _vp, _u32, C.POINTER(Options), C.POINTER(_vp)]
+        L.fmmds_batch_create.restype = C.c_int
+        L.fmmds_batch_launch.argtypes = [_vp, _vp, C.c_int]
+        L.fmmds_batch_launch.restype = C.c_int
+        L.fmmds_batch_wait.argtypes = [_vp]
+        L.fmmds_batch_wait.restype = C.c_int
+        L.fmmds_batch_tree.argtypes = [_vp, _u32]
+        L.fmmds_batch_tree.restype = C.POINTER(TreeStruct)
+        L.fmmds_batch_sort_items.argtypes = [_vp]
+        L.fmmds_batch_sort_items.restype = _u32
+        L.fmmds_batch_free.argtypes = [_vp]
+        L.fmmds_batch_free.restype = None
         L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
         L.fmmds_profile_enable.restype = None
         L.fmmds_profile_reset.restype = None
@@ -100,7 +112,9 @@ def _lib():
 def exported_symbols():
     return ["fmmds_build", "fmmds_neighbors", "fmmds_interactions", "fmmds_free",
             "fmmds_trim", "fmmds_profile_enable", "fmmds_profile_reset",
-            "fmmds_profile_read", "fmmds_status_string"]
+            "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
+            "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
+            "fmmds_batch_sort_items", "fmmds_batch_free"]
 
 
 def trim():
@@ -161,9 +175,10 @@ _TORCH_ALLOC = None
 class Tree:
     """A built tree: device tables and lists owned by libfmmds."""
 
-    def __init__(self, handle, allocator=None):
+    def __init__(self, handle, allocator=None, owner=None):
         self._h = handle
         self._alloc = allocator  # keeps callbacks alive as long as the tree
+        self._owner = owner      # a Batch: this tree is a view into it
         t = handle.contents
         self.depth = int(t.depth)
         self.key_bits = int(t.key_bits)
@@ -175,7 +190,8 @@ class Tree:
     # -- lifetime
     def free(self):
         if self._h is not None:
-            _lib().fmmds_free(self._h)
+            if self._owner is None:
+                _lib().fmmds_free(self._h)
             self._h = None
 
     def __enter__(self):
@@ -305,3 +321,69 @@ def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int 
     if st != OK:
         raise FmmdsError(st, "fmmds_build")
     return Tree(out, keep)
+
+
+class Batch:
+    """Batched build of many point sets (fmmds_batch_*): plan once, launch
+    many times (optionally as a replayed HIP graph), read per-set trees."""
+
+    def __init__(self, set_offsets, levels, *, stream=None, allocator: str = "pool"):
+        import torch
+        L = _lib()
+        self._off = np.ascontiguousarray(set_offsets, dtype=np.uint64)
+        self._lev = np.ascontiguousarray(levels, dtype=np.uint8)
+        self.n_sets = int(self._lev.size)
+        opt = Options()
+        opt.key_bits, opt.cluster_s, opt.max_level, opt.reserved = 64, 0, 21, 0
+        self._stream = stream
+        opt.stream = stream.cuda_stream if stream is not None else None
+        self._keep = None
+        if allocator == "torch":
+            global _TORCH_ALLOC
+            if _TORCH_ALLOC is None:
+                _TORCH_ALLOC = _TorchAllocator()
+            self._keep = _TORCH_ALLOC
+            opt.alloc, opt.release = self._keep.alloc, self._keep.release
+        h = _vp()
+        st = L.fmmds_batch_create(self._off.ctypes.data_as(_vp), self._lev.ctypes.data_as(_vp),
+                                  self.n_sets, C.byref(opt), C.byref(h))
+        if st != OK:
+            raise FmmdsError(st, "fmmds_batch_create")
+        self._h = h
+        self._torch = torch
+
+    def launch(self, xyz, capture: bool = False):
+        """Enqueue a build of the concatenated coordinates (float32 CUDA
+        tensor (total, 3)). Work queued on the current stream before this call
+        is complete before the batch reads xyz."""
+        if self._stream is None:
+            self._torch.cuda.current_stream().synchronize()
+        st = _lib().fmmds_batch_launch(self._h, xyz.data_ptr(), 1 if capture else 0)
+        if st != OK:
+            raise FmmdsError(st, "fmmds_batch_launch")
+
+    def wait(self):
+        st = _lib().fmmds_batch_wait(self._h)
+        if st != OK:
+            raise FmmdsError(st, "fmmds_batch_wait")
+
+    def tree(self, i: int) -> Tree:
+        t = _lib().fmmds_batch_tree(self._h, i)
+        if not t:
+            raise RuntimeError("no tree: launch and wait first")
+        return Tree(t, owner=self)
+
+    @property
+    def sort_items(self) -> int:
+        return int(_lib().fmmds_batch_sort_items(self._h))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            _lib().fmmds_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -11,8 +11,7 @@ constexpr int kMaxPasses = 8;  // 63 key bits / 8-bit digits
 
 // Tile shapes of the single-pass kernels.
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 elements
+constexpr int kSortItemsDefault = 16;  // tile = 256 * items elements (8, 12 or 16)
 constexpr int kCompBlock = 256;
 constexpr int kCompItems = 8;
 constexpr int kCompTile = kCompBlock * kCompItems;  // 2048 elements
@@ -41,15 +40,16 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
                    uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err, hipStream_t s);
 void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass, hipStream_t s);
+uint32_t sort_tiles(uint32_t n, int items);
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
-                      uint64_t* status, uint32_t* tile_counter, hipStream_t s);
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items);
 
 // ---- tables.hip
 void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
                  const float* xyz, uint32_t n, uint32_t* perm, float* sorted_xyz, void* leaf_key,
                  uint32_t* leaf_begin, uint64_t* status, uint32_t* tile_counter, uint32_t* n_out,
-                 hipStream_t s);
+                 hipStream_t s, const uint64_t* set_off = nullptr, uint32_t set_shift = 0);
 void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32_t* n_in,
                   uint32_t cap_in, uint32_t n_points, void* kout, uint32_t* bout, uint32_t* cout,
                   uint8_t* mout, uint32_t* pout, uint64_t* status, uint32_t* tile_counter,
@@ -71,6 +71,16 @@ struct ListLevelArgs {
   const uint32_t* e2_ent_up;
   uint32_t up_all;              // level - 1 == 1: E2 there is every source box
   uint32_t n_src_up;            // source boxes at level - 1
+  // Batch only (first_up == nullptr otherwise): keys carry the set id from
+  // bit 3 * (level - 1) up (at level - 1); a set's boxes at a level occupy
+  // ranks [first[set], first[set + 1]); sets shallower than `level` get empty
+  // lists; entries are written relative to first_cur[set].
+  const uint32_t* first_up;     // level - 1
+  const uint32_t* first_cur;    // level
+  const uint8_t* set_level;     // per set
+  uint32_t key_bits_up;         // bits of the level - 1 keys including the set id
+  const uint32_t* n_recv_up_dev;// if set, the parent count is read here and
+                                // n_recv_up is only the capacity
 };
 void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                        hipStream_t s);
@@ -78,6 +88,26 @@ void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
                       const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s);
 void launch_scan_counts(const uint32_t* cnt, uint32_t n, uint32_t* off, uint64_t* total,
                         uint32_t* overflow, uint64_t* status, uint32_t* tile_counter,
-                        hipStream_t s);
+                        hipStream_t s, const uint32_t* n_dev = nullptr);
+
+// ---- batch.hip kernels
+struct LevelPtrs {
+  const uint32_t* begin[kMaxLevel + 1];
+};
+void launch_batch_keygen(const float* xyz, uint32_t n, const uint64_t* set_off, uint32_t n_sets,
+                         const uint8_t* set_level, uint32_t L_all, bool packed, uint64_t* keys,
+                         uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
+                         hipStream_t s);
+void launch_batch_first(const LevelPtrs& lp, uint32_t L_all, const uint32_t* n_boxes,
+                        const uint64_t* set_off, uint32_t n_sets, uint32_t* first, hipStream_t s);
+void launch_batch_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
+                         const uint32_t* gbegin, const uint32_t* gparent, const uint32_t* gchild,
+                         const uint32_t* first_prev, const uint32_t* first_cur,
+                         const uint32_t* first_next, const uint64_t* set_off, uint64_t* fkey,
+                         uint32_t* fbegin, uint32_t* fparent, uint32_t* fchild, hipStream_t s);
+void launch_batch_list_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
+                              const uint32_t* first_cur, const uint32_t* goff2,
+                              const uint32_t* goff4, uint32_t* loff2, uint32_t* loff4,
+                              uint32_t* base2, uint32_t* base4, uint32_t n_sets, hipStream_t s);
 
 }  // namespace fmmds

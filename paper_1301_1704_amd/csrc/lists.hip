@@ -77,8 +77,11 @@ __global__ __launch_bounds__(256) void k_lists(
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
   const uint32_t j = threadIdx.x & 31u, h = threadIdx.x >> 5;
   const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
-  if (p >= a.n_recv_up) return;  // whole half-wave
-  uint32_t j0, cnt;
+  const uint32_t n_up = a.n_recv_up_dev ? *a.n_recv_up_dev : a.n_recv_up;
+  if (p >= n_up) return;  // whole half-wave
+  // upbase: batch rank of the set's first box at level - 1 (parent-level E2
+  // entries are stored relative to it); base: the same at level l.
+  uint32_t j0, cnt, upbase = 0, base = 0;
   if (a.up_all) {
     j0 = 0;
     cnt = a.n_src_up;
@@ -86,19 +89,26 @@ __global__ __launch_bounds__(256) void k_lists(
     j0 = a.e2_off_up[p];
     cnt = a.e2_off_up[p + 1] - j0;
   }
+  if (a.first_up) {
+    const uint32_t set = (uint32_t)((uint64_t)pkey[p] >> (3 * (a.level - 1)));
+    base = a.first_cur[set];
+    upbase = a.first_up[set];
+    if (a.up_all) cnt = a.first_up[set + 1] - upbase;
+    if (a.set_level[set] < a.level) cnt = 0;  // the set's lists stop above this level
+  }
   const uint32_t rmask = a.recv_mask_up[p];
   const uint32_t rfirst = a.recv_child_up[p];
   uint32_t m = 0, cb = 0, wa = 0, wb = 0;
   uint32_t ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
   if (j < cnt) {
-    const uint32_t s = a.up_all ? j : a.e2_ent_up[j0 + j];
+    const uint32_t s = upbase + (a.up_all ? j : a.e2_ent_up[j0 + j]);
     const A sk = (A)skey[s], pk = (A)pkey[p];
     const A X = (A)kAxisX;
     const int dx = axis_delta<A>(sk, pk, X, (A)1);
     const int dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
     const int dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
     m = a.src_mask_up[s];
-    if (MODE == 1) cb = a.src_child_up[s];
+    if (MODE == 1) cb = a.src_child_up[s] - base;
     // Children of s adjacent to a receiver child whose axis bit is 0 / 1:
     // offset 0: all; +1: child bit 0 and receiver bit 1; -1: child bit 1 and
     // receiver bit 0. Octants with the x / y / z bit clear: 0x55 / 0x33 / 0x0F.
@@ -185,9 +195,9 @@ template <int MODE>
 void launch_lists(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                   const uint32_t* off2, const uint32_t* off4, uint32_t* ent2, uint32_t* ent4,
                   hipStream_t s) {
-  if (a.n_recv_up == 0) return;
+  if (a.n_recv_up == 0) return;  // with n_recv_up_dev: the capacity
   const uint32_t grid = div_up(a.n_recv_up, 8);
-  const bool narrow = 3 * (a.level - 1) <= 32;  // parent-level keys fit 32 bits
+  const bool narrow = a.key_bits_up <= 32;  // parent-level keys fit 32 bits
   if (key64 && narrow)
     hipLaunchKernelGGL((k_lists<uint64_t, uint32_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
                        cnt4, off2, off4, ent2, ent4);
@@ -216,16 +226,18 @@ void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
 // if it does not fit 32-bit offsets.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kCompBlock) void k_scan_counts(
-    const uint32_t* __restrict__ cnt, uint32_t n, uint32_t* __restrict__ off,
-    uint64_t* __restrict__ total, uint32_t* __restrict__ overflow, uint64_t* __restrict__ status,
-    uint32_t* __restrict__ tile_counter) {
+    const uint32_t* __restrict__ cnt, uint32_t n_host, const uint32_t* __restrict__ n_dev,
+    uint32_t* __restrict__ off, uint64_t* __restrict__ total, uint32_t* __restrict__ overflow,
+    uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter) {
   __shared__ uint32_t s_w[kCompBlock / 64];
   __shared__ uint64_t s_excl;
   __shared__ uint32_t s_tile;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
+  if ((uint64_t)tile * kCompTile >= n) return;  // whole block: surplus tile
   const uint64_t base = (uint64_t)tile * kCompTile + (uint64_t)tid * kCompItems;
   uint32_t v[kCompItems];
   uint32_t sum = 0;
@@ -267,10 +279,11 @@ __global__ __launch_bounds__(kCompBlock) void k_scan_counts(
 
 void launch_scan_counts(const uint32_t* cnt, uint32_t n, uint32_t* off, uint64_t* total,
                         uint32_t* overflow, uint64_t* status, uint32_t* tile_counter,
-                        hipStream_t s) {
+                        hipStream_t s, const uint32_t* n_dev) {
+  // n is the exact count, or with n_dev the capacity (the count is read there)
   if (n == 0) return;
   hipLaunchKernelGGL(k_scan_counts, dim3(div_up(n, kCompTile)), dim3(kCompBlock), 0, s, cnt, n,
-                     off, total, overflow, status, tile_counter);
+                     n_dev, off, total, overflow, status, tile_counter);
 }
 
 }  // namespace fmmds

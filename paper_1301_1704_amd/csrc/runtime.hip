@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <tuple>
 #include <cstring>
 #include <map>
 #include <new>
@@ -213,6 +214,7 @@ struct ListBufs {
 };
 
 struct TreeImpl {
+  bool view = false;  // a set of a batch: owned by the batch, fmmds_free ignores it
   Allocator A;
   Pool outs;
   ListBufs lists[kMaxLevel + 1];
@@ -249,12 +251,12 @@ void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 enum KernelClass {
   K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
-  K_NCLASS
+  K_REBASE, K_NCLASS
 };
 const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
                                           "sort_pass", "leaf",        "level",
                                           "max_occupancy", "list_count", "scan_counts",
-                                          "list_fill"};
+                                          "list_fill",     "batch_rebase"};
 
 struct ClassStat {
   uint64_t launches = 0;
@@ -384,7 +386,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     size_t words = 0, tickets = 0;
     for (int s = 0; s < nsets; ++s) {
       const uint32_t n = sets[s].n;
-      words += (size_t)n_pass * div_up(n, kSortTile) * 256 + div_up(n, kCompTile);
+      words += (size_t)n_pass * sort_tiles(n, kSortItemsDefault) * 256 + div_up(n, kCompTile);
       for (uint32_t l = 0; l < L; ++l) words += div_up(level_cap(n, l + 1), kCompTile);
       tickets += n_pass + 1 + L;
     }
@@ -455,11 +457,11 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       for (uint32_t p = 0; p < n_pass; ++p) {
         const int a = p & 1, b = a ^ 1;
         const uint32_t shift = (packed ? 32 : 0) + 8 * p;
-        uint64_t* stw = sa.take_words((size_t)div_up(n, kSortTile) * 256);
+        uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
         uint32_t* tk = sa.take_ticket();
         P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
           launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,
-                           stw, tk, st);
+                           stw, tk, st, kSortItemsDefault);
         });
       }
       const int fin = n_pass & 1;
@@ -543,6 +545,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       a.src_child_up = sets[0].lv[l - 1].child;
       a.up_all = (l - 1 == 1) ? 1u : 0u;
       a.n_src_up = nb[0][l - 1];
+      a.key_bits_up = 3 * (l - 1);
       if (!a.up_all) {
         a.e2_off_up = impl->lists[l - 1].off[0];
         a.e2_ent_up = impl->lists[l - 1].ent[0];
@@ -630,6 +633,469 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
   return FMMDS_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched form (fmmds_batch_*).
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  uint32_t log2n, n_pass, packed;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(log2n, n_pass, packed) < std::tie(o.log2n, o.n_pass, o.packed);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // sort tile size chosen by timing, per shape class
+
+struct BatchImpl {
+  uint32_t n_sets = 0, P = 0, L = 0, setbits = 0, keybits = 0, n_pass = 0;
+  bool packed = false;
+  int items = kSortItemsDefault;
+  std::vector<uint64_t> off;
+  std::vector<uint8_t> lev;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Allocator A;
+  Pool mem;
+  uint64_t* d_off = nullptr;
+  uint8_t* d_lev = nullptr;
+  SortBufs sb{};
+  uint32_t* perm = nullptr;
+  float* sxyz = nullptr;
+  LevelBufs g[kMaxLevel + 1];
+  uint64_t* fkey[kMaxLevel + 1] = {};
+  uint32_t* fbegin[kMaxLevel + 1] = {};
+  uint32_t* fparent[kMaxLevel + 1] = {};
+  uint32_t* fchild[kMaxLevel + 1] = {};
+  uint32_t cap[kMaxLevel + 1] = {}, rcap[kMaxLevel + 1] = {};
+  uint32_t* cnt = nullptr;
+  uint32_t* goff[kMaxLevel + 1][2] = {};
+  uint32_t* loff[kMaxLevel + 1][2] = {};
+  uint32_t* ent[kMaxLevel + 1][2] = {};
+  // device block copied back after each launch: DevMeta, first, bases
+  char* dblock = nullptr;
+  size_t dblock_b = 0, first_at = 0, base_at = 0;
+  char* hblock = nullptr;  // pinned mirror
+  // zeroed per launch: dblock, histograms, digit offsets, tickets, status words
+  char* ws = nullptr;
+  size_t ws_b = 0, hist_at = 0, goffd_at = 0, tick_at = 0, words_at = 0;
+  size_t n_words = 0, n_tickets = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const float* graph_xyz = nullptr;
+  bool launched = false;
+  std::vector<fmmds_tree> trees;
+  std::vector<TreeImpl> views;
+
+  DevMeta* meta() const { return (DevMeta*)dblock; }
+  uint32_t* first() const { return (uint32_t*)(dblock + first_at); }
+  uint32_t* first_l(uint32_t l) const { return first() + (size_t)l * (n_sets + 1); }
+  uint32_t* base(uint32_t l, int k) const {
+    return (uint32_t*)(dblock + base_at) + ((size_t)(l * 2 + k)) * (n_sets + 1);
+  }
+};
+
+void batch_sort_passes(BatchImpl& B, StatusArena& sa, Prof& P, int items) {
+  uint32_t* goffd = (uint32_t*)(B.ws + B.goffd_at);
+  for (uint32_t p = 0; p < B.n_pass; ++p) {
+    const int a = p & 1, b = a ^ 1;
+    const uint32_t shift = (B.packed ? 32 : 0) + 8 * p;
+    uint64_t* stw = sa.take_words((size_t)sort_tiles(B.P, items) * 256);
+    uint32_t* tk = sa.take_ticket();
+    P.run(K_SORT, (double)B.P * (B.packed ? 16 : 24), [&] {
+      launch_sort_pass(B.packed, B.sb.k[a], B.sb.k[b], B.sb.v[a], B.sb.v[b], B.P, shift,
+                       goffd + p * 256, stw, tk, B.stream, items);
+    });
+  }
+}
+
+void batch_front(BatchImpl& B, const float* xyz, StatusArena& sa, Prof& P) {
+  const hipStream_t st = B.stream;
+  sa = StatusArena();
+  sa.tickets = (uint32_t*)(B.ws + B.tick_at);
+  sa.n_tickets = B.n_tickets;
+  sa.words = (uint64_t*)(B.ws + B.words_at);
+  sa.n_words = B.n_words;
+  P.run(K_ZERO, (double)B.ws_b, [&] { launch_zero(B.ws, B.ws_b, st); });
+  uint32_t* hist = (uint32_t*)(B.ws + B.hist_at);
+  uint32_t* goffd = (uint32_t*)(B.ws + B.goffd_at);
+  P.run(K_KEYGEN, (double)B.P * (12 + 8 + (B.packed ? 0 : 4)), [&] {
+    launch_batch_keygen(xyz, B.P, B.d_off, B.n_sets, B.d_lev, B.L, B.packed, B.sb.k[0],
+                        B.sb.v[0], B.n_pass, hist, &B.meta()->err_range, st);
+  });
+  P.run(K_DIGITS, (double)B.n_pass * 2048, [&] { launch_digit_offsets(hist, goffd, B.n_pass, st); });
+}
+
+void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
+  const hipStream_t st = B.stream;
+  const uint32_t L = B.L;
+  StatusArena sa;
+  batch_front(B, xyz, sa, P);
+  batch_sort_passes(B, sa, P, B.items);
+  const int fin = B.n_pass & 1;
+  DevMeta* meta = B.meta();
+  {
+    uint64_t* stw = sa.take_words(div_up(B.P, kCompTile));
+    uint32_t* tk = sa.take_ticket();
+    P.run(K_LEAF, (double)B.P * ((B.packed ? 8 : 12) + 4 + 12 + 12), [&] {
+      launch_leaf(B.packed, true, B.sb.k[fin], B.sb.v[fin], xyz, B.P, B.perm, B.sxyz, B.g[L].key,
+                  B.g[L].begin, stw, tk, &meta->n_boxes[0][L], st, B.d_off, 3 * L);
+    });
+  }
+  for (int l = (int)L - 1; l >= 0; --l) {
+    LevelBufs& up = B.g[l];
+    LevelBufs& dn = B.g[l + 1];
+    uint64_t* stw = sa.take_words(div_up(dn.cap, kCompTile));
+    uint32_t* tk = sa.take_ticket();
+    P.run(K_LEVEL, 0.0, [&] {
+      launch_level(true, dn.key, dn.begin, &meta->n_boxes[0][l + 1], dn.cap, B.P, up.key,
+                   up.begin, up.child, up.mask, dn.parent, stw, tk, &meta->n_boxes[0][l], st);
+    });
+  }
+  LevelPtrs lp{};
+  for (uint32_t l = 0; l <= L; ++l) lp.begin[l] = B.g[l].begin;
+  P.run(K_REBASE, 0.0, [&] {
+    launch_batch_first(lp, L, meta->n_boxes[0], B.d_off, B.n_sets, B.first(), st);
+  });
+  for (uint32_t l = 0; l <= L; ++l) {
+    P.run(K_REBASE, 0.0, [&] {
+      launch_batch_rebase(l, B.cap[l], &meta->n_boxes[0][l], (const uint64_t*)B.g[l].key,
+                          B.g[l].begin, l >= 1 ? B.g[l].parent : nullptr,
+                          l < L ? B.g[l].child : nullptr, l >= 1 ? B.first_l(l - 1) : nullptr,
+                          B.first_l(l), l < L ? B.first_l(l + 1) : nullptr, B.d_off, B.fkey[l],
+                          B.fbegin[l], B.fparent[l], B.fchild[l], st);
+    });
+  }
+  for (uint32_t l = 2; l <= L; ++l) {
+    ListLevelArgs a{};
+    a.level = l;
+    a.n_recv_up = B.cap[l - 1];
+    a.n_recv_up_dev = &meta->n_boxes[0][l - 1];
+    a.recv_key_up = B.g[l - 1].key;
+    a.recv_mask_up = B.g[l - 1].mask;
+    a.recv_child_up = B.g[l - 1].child;
+    a.src_key_up = B.g[l - 1].key;
+    a.src_mask_up = B.g[l - 1].mask;
+    a.src_child_up = B.g[l - 1].child;
+    a.up_all = l == 2 ? 1u : 0u;
+    if (!a.up_all) {
+      a.e2_off_up = B.goff[l - 1][0];
+      a.e2_ent_up = B.ent[l - 1][0];
+    }
+    a.first_up = B.first_l(l - 1);
+    a.first_cur = B.first_l(l);
+    a.set_level = B.d_lev;
+    a.key_bits_up = B.setbits + 3 * (l - 1);
+    uint32_t* c2 = B.cnt;
+    uint32_t* c4 = B.cnt + B.cap[l];
+    P.run(K_COUNT, 0.0, [&] { launch_list_count(true, a, c2, c4, st); });
+    for (int k = 0; k < 2; ++k) {
+      uint64_t* stw = sa.take_words(div_up(B.cap[l], kCompTile));
+      uint32_t* tk = sa.take_ticket();
+      P.run(K_SCAN, 0.0, [&] {
+        launch_scan_counts(k == 0 ? c2 : c4, B.cap[l], B.goff[l][k], &meta->list_total[k][l],
+                           &meta->overflow, stw, tk, st, &meta->n_boxes[0][l]);
+      });
+    }
+    P.run(K_FILL, 0.0, [&] {
+      launch_list_fill(true, a, B.goff[l][0], B.goff[l][1], B.ent[l][0], B.ent[l][1], st);
+    });
+    P.run(K_REBASE, 0.0, [&] {
+      launch_batch_list_rebase(l, B.cap[l], &meta->n_boxes[0][l], (const uint64_t*)B.g[l].key,
+                               B.first_l(l), B.goff[l][0], B.goff[l][1], B.loff[l][0],
+                               B.loff[l][1], B.base(l, 0), B.base(l, 1), B.n_sets, st);
+    });
+  }
+  ck(hipMemcpyAsync(B.hblock, B.dblock, B.dblock_b, hipMemcpyDeviceToHost, st));
+}
+
+// Times each sort tile size on this batch's real keys; keeps the fastest.
+int batch_autotune(BatchImpl& B, const float* xyz) {
+  const TuneKey key{(uint32_t)(63 - __builtin_clzll((uint64_t)B.P | 1)), B.n_pass,
+                    B.packed ? 1u : 0u};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  Prof off;
+  hipEvent_t e0, e1;
+  ck(hipEventCreate(&e0));
+  ck(hipEventCreate(&e1));
+  int best = kSortItemsDefault;
+  float best_ms = 1e30f;
+  for (int items : {8, 12, 16}) {
+    float total = 0;
+    for (int rep = 0; rep < 2; ++rep) {
+      StatusArena sa;
+      batch_front(B, xyz, sa, off);
+      ck(hipEventRecord(e0, B.stream));
+      batch_sort_passes(B, sa, off, items);
+      ck(hipEventRecord(e1, B.stream));
+      ck(hipEventSynchronize(e1));
+      float ms = 0;
+      ck(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1) total = ms;  // the first run warms caches and code
+    }
+    if (total < best_ms) {
+      best_ms = total;
+      best = items;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
+fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
+                          const fmmds_options* opt, fmmds_batch** out) {
+  if (!set_offsets || !levels || !opt || n_sets == 0) return FMMDS_ERR_ARG;
+  if (opt->key_bits != 64 || opt->cluster_s != 0 || opt->reserved != 0 ||
+      ((opt->alloc == nullptr) != (opt->release == nullptr)))
+    return FMMDS_ERR_ARG;
+  if (set_offsets[0] != 0) return FMMDS_ERR_ARG;
+  uint32_t L = 0;
+  for (uint32_t i = 0; i < n_sets; ++i) {
+    if (set_offsets[i + 1] <= set_offsets[i]) return FMMDS_ERR_ARG;
+    if (levels[i] < 2 || levels[i] > FMMDS_MAX_LEVEL) return FMMDS_ERR_ARG;
+    L = std::max<uint32_t>(L, levels[i]);
+  }
+  if (set_offsets[n_sets] >= 0xFFFFFFFFull) return FMMDS_ERR_ARG;
+  uint32_t setbits = 1;
+  while ((1ull << setbits) < n_sets) ++setbits;
+  if (setbits + 3 * L > 64) return FMMDS_ERR_ARG;
+
+  BatchImpl* B = new (std::nothrow) BatchImpl();
+  if (!B) return FMMDS_ERR_NOMEM;
+  fmmds_status result = FMMDS_OK;
+  try {
+    B->n_sets = n_sets;
+    B->P = (uint32_t)set_offsets[n_sets];
+    B->L = L;
+    B->setbits = setbits;
+    B->keybits = setbits + 3 * L;
+    B->packed = B->keybits <= 32;
+    B->n_pass = div_up(B->keybits, 8);
+    B->off.assign(set_offsets, set_offsets + n_sets + 1);
+    B->lev.assign(levels, levels + n_sets);
+    if (opt->stream) {
+      B->stream = (hipStream_t)opt->stream;
+    } else {
+      ck(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+      B->own_stream = true;
+    }
+    B->A.alloc = opt->alloc;
+    B->A.release = opt->release;
+    B->A.ctx = opt->alloc_ctx;
+    B->A.stream = B->stream;
+    B->mem.A = &B->A;
+    const uint32_t P = B->P;
+    // capacities: boxes of set i at level l are at most min(n_i, 8^min(l, L_i))
+    for (uint32_t l = 0; l <= L; ++l) {
+      uint64_t c = 0, r = 0;
+      for (uint32_t i = 0; i < n_sets; ++i) {
+        const uint64_t ni = set_offsets[i + 1] - set_offsets[i];
+        const uint32_t e = std::min<uint32_t>(l, levels[i]);
+        const uint64_t boxes = std::min<uint64_t>(ni, 1ull << (3 * e));
+        c += boxes;
+        if (levels[i] >= l) r += boxes;
+      }
+      B->cap[l] = (uint32_t)c;
+      B->rcap[l] = (uint32_t)r;
+      if (l >= 2 && 189ull * r > 0xFFFFFFFFull) throw Fail{FMMDS_ERR_OVERFLOW};
+    }
+    Pool& M = B->mem;
+    B->d_off = M.get<uint64_t>(n_sets + 1);
+    B->d_lev = M.get<uint8_t>(n_sets);
+    ck(hipMemcpyAsync(B->d_off, set_offsets, (n_sets + 1) * 8, hipMemcpyHostToDevice, B->stream));
+    ck(hipMemcpyAsync(B->d_lev, levels, n_sets, hipMemcpyHostToDevice, B->stream));
+    B->sb.k[0] = M.get<uint64_t>(P);
+    B->sb.k[1] = M.get<uint64_t>(P);
+    if (!B->packed) {
+      B->sb.v[0] = M.get<uint32_t>(P);
+      B->sb.v[1] = M.get<uint32_t>(P);
+    }
+    B->perm = M.get<uint32_t>(P);
+    B->sxyz = M.get<float>(3 * (size_t)P);
+    uint32_t cmax = 0;
+    for (uint32_t l = 0; l <= L; ++l) {
+      const size_t c = B->cap[l];
+      cmax = std::max<uint32_t>(cmax, (uint32_t)c);
+      LevelBufs& G = B->g[l];
+      G.cap = (uint32_t)c;
+      G.key = M.get<uint64_t>(c);
+      G.begin = M.get<uint32_t>(c + 1);
+      if (l >= 1) G.parent = M.get<uint32_t>(c);
+      if (l < L) {
+        G.child = M.get<uint32_t>(c + 1);
+        G.mask = M.get<uint8_t>(c);
+      }
+      B->fkey[l] = M.get<uint64_t>(c);
+      B->fbegin[l] = M.get<uint32_t>(c + n_sets);
+      if (l >= 1) B->fparent[l] = M.get<uint32_t>(c);
+      if (l < L) B->fchild[l] = M.get<uint32_t>(c + n_sets);
+      if (l >= 2) {
+        for (int k = 0; k < 2; ++k) {
+          B->goff[l][k] = M.get<uint32_t>(c + 1);
+          B->loff[l][k] = M.get<uint32_t>(c + n_sets);
+          B->ent[l][k] = M.get<uint32_t>((size_t)(k == 0 ? 27 : 189) * B->rcap[l]);
+        }
+      }
+    }
+    B->cnt = M.get<uint32_t>(2 * (size_t)std::max<uint32_t>(cmax, 1));
+    // metadata block and the zeroed workspace around it
+    B->first_at = round_up(sizeof(DevMeta), 256);
+    B->base_at = round_up(B->first_at + (size_t)(L + 1) * (n_sets + 1) * 4, 256);
+    B->dblock_b = round_up(B->base_at + (size_t)(L + 1) * 2 * (n_sets + 1) * 4, 256);
+    B->hist_at = B->dblock_b;
+    B->goffd_at = B->hist_at + round_up(kMaxPasses * 256 * 4, 256);
+    B->tick_at = B->goffd_at + round_up(kMaxPasses * 256 * 4, 256);
+    B->n_tickets = B->n_pass + 1 + L + 2 * (L + 1);
+    B->words_at = B->tick_at + round_up(B->n_tickets * 4, 256);
+    size_t words = (size_t)B->n_pass * sort_tiles(P, 8) * 256 + div_up(P, kCompTile);
+    for (uint32_t l = 0; l < L; ++l) words += div_up(B->cap[l + 1], kCompTile);
+    for (uint32_t l = 2; l <= L; ++l) words += 2 * (size_t)div_up(B->cap[l], kCompTile);
+    B->n_words = words;
+    B->ws_b = round_up(B->words_at + words * 8, 256);
+    B->ws = M.get<char>(B->ws_b);
+    B->dblock = B->ws;
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, B->dblock_b, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{FMMDS_ERR_NOMEM};
+    }
+    B->hblock = (char*)hp;
+    B->trees.assign(n_sets, fmmds_tree());
+    B->views.resize(n_sets);
+    for (uint32_t i = 0; i < n_sets; ++i) B->views[i].view = true;
+    ck(hipStreamSynchronize(B->stream));
+  } catch (const Fail& f) {
+    result = f.st;
+  } catch (const std::bad_alloc&) {
+    result = FMMDS_ERR_NOMEM;
+  }
+  if (result != FMMDS_OK) {
+    (void)hipGetLastError();
+    B->mem.release_all();
+    if (B->hblock) (void)hipHostFree(B->hblock);
+    if (B->own_stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+    return result;
+  }
+  *out = (fmmds_batch*)B;
+  return FMMDS_OK;
+}
+
+fmmds_status batch_launch(BatchImpl* B, const float* xyz, int capture) {
+  if (!B || !xyz) return FMMDS_ERR_ARG;
+  try {
+    if (capture) {
+      if (B->exec && B->graph_xyz != xyz) return FMMDS_ERR_ARG;
+      if (!B->exec) {
+        B->items = batch_autotune(*B, xyz);
+        Prof off;
+        ck(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        try {
+          batch_enqueue(*B, xyz, off);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(B->stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        ck(hipStreamEndCapture(B->stream, &B->graph));
+        ck(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        B->graph_xyz = xyz;
+      }
+      ck(hipGraphLaunch(B->exec, B->stream));
+    } else {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(TuneKey{(uint32_t)(63 - __builtin_clzll((uint64_t)B->P | 1)),
+                                    B->n_pass, B->packed ? 1u : 0u});
+      if (it != g_tune.end()) B->items = it->second;
+    }
+    if (!capture) {
+      Prof P;
+      P.on = g_prof_on.load() != 0;
+      P.only = g_prof_only.load();
+      P.s = B->stream;
+      batch_enqueue(*B, xyz, P);
+      P.finish([](const Prof::Rec&) { return 0.0; });
+    }
+    B->launched = true;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.st;
+  }
+  return FMMDS_OK;
+}
+
+fmmds_status batch_wait(BatchImpl* B) {
+  if (!B || !B->launched) return FMMDS_ERR_ARG;
+  try {
+    ck(hipStreamSynchronize(B->stream));
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  const DevMeta* hm = (const DevMeta*)B->hblock;
+  if (hm->err_range) return FMMDS_ERR_RANGE;
+  if (hm->overflow) return FMMDS_ERR_OVERFLOW;
+  const uint32_t* first = (const uint32_t*)(B->hblock + B->first_at);
+  const uint32_t* base = (const uint32_t*)(B->hblock + B->base_at);
+  const uint32_t ns = B->n_sets;
+  for (uint32_t i = 0; i < ns; ++i) {
+    fmmds_tree& t = B->trees[i];
+    TreeImpl& v = B->views[i];
+    const uint32_t Li = B->lev[i];
+    const uint64_t o = B->off[i];
+    std::memset(&t, 0, sizeof(t));
+    t.depth = Li;
+    t.key_bits = 64;
+    t.max_level = Li;
+    t.shared = 1;
+    t.n_src = t.n_recv = (uint32_t)(B->off[i + 1] - o);
+    t.src_perm = t.recv_perm = B->perm + o;
+    t.src_sorted_xyz = t.recv_sorted_xyz = B->sxyz + 3 * o;
+    for (uint32_t l = 0; l <= Li; ++l) {
+      const uint32_t f = first[(size_t)l * (ns + 1) + i];
+      const uint32_t nl = first[(size_t)l * (ns + 1) + i + 1] - f;
+      fmmds_level& lv = t.src[l];
+      lv.n = nl;
+      lv.key = B->fkey[l] + f;
+      lv.begin = B->fbegin[l] + f + i;
+      lv.parent = l >= 1 ? B->fparent[l] + f : nullptr;
+      lv.child = l < Li ? B->fchild[l] + f + i : nullptr;
+      t.recv[l] = lv;
+      if (l >= 2) {
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t* bk = base + ((size_t)(l * 2 + k)) * (ns + 1);
+          v.lists[l].off[k] = B->loff[l][k] + f + i;
+          v.lists[l].ent[k] = B->ent[l][k] + bk[i];
+          v.lists[l].total[k] = bk[i + 1] - bk[i];
+        }
+        v.n_recv_boxes[l] = nl;
+      }
+    }
+    t.impl = &v;
+  }
+  return FMMDS_OK;
+}
+
+void batch_free(BatchImpl* B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->stream);
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->mem.release_all();
+  if (B->hblock) (void)hipHostFree(B->hblock);
+  if (B->own_stream) {
+    (void)hipStreamSynchronize(B->stream);
+    (void)hipStreamDestroy(B->stream);
+  }
+  delete B;
+}
+
 fmmds_status list_query(const fmmds_tree* t, int kind, uint32_t level, const uint32_t** offsets,
                         const uint32_t** entries, uint32_t* n_recv_boxes, uint64_t* n_entries) {
   if (!t || !t->impl || !offsets || !entries || !n_recv_boxes || !n_entries) return FMMDS_ERR_ARG;
@@ -670,12 +1136,40 @@ fmmds_status fmmds_interactions(const fmmds_tree* t, uint32_t level, const uint3
 void fmmds_free(fmmds_tree* t) {
   if (!t) return;
   fmmds::TreeImpl* impl = (fmmds::TreeImpl*)t->impl;
+  if (impl && impl->view) return;
   if (impl) {
     impl->outs.release_all();
     delete impl;
   }
   delete t;
 }
+
+fmmds_status fmmds_batch_create(const uint64_t* set_offsets, const uint8_t* levels,
+                                uint32_t n_sets, const fmmds_options* opt, fmmds_batch** out) {
+  if (!out) return FMMDS_ERR_ARG;
+  *out = nullptr;
+  return fmmds::batch_create(set_offsets, levels, n_sets, opt, out);
+}
+
+fmmds_status fmmds_batch_launch(fmmds_batch* b, const float* xyz, int capture) {
+  return fmmds::batch_launch((fmmds::BatchImpl*)b, xyz, capture);
+}
+
+fmmds_status fmmds_batch_wait(fmmds_batch* b) {
+  return fmmds::batch_wait((fmmds::BatchImpl*)b);
+}
+
+const fmmds_tree* fmmds_batch_tree(const fmmds_batch* b, uint32_t set) {
+  const fmmds::BatchImpl* B = (const fmmds::BatchImpl*)b;
+  if (!B || set >= B->n_sets || B->trees[set].impl == nullptr) return nullptr;
+  return &B->trees[set];
+}
+
+uint32_t fmmds_batch_sort_items(const fmmds_batch* b) {
+  return b ? (uint32_t)((const fmmds::BatchImpl*)b)->items : 0;
+}
+
+void fmmds_batch_free(fmmds_batch* b) { fmmds::batch_free((fmmds::BatchImpl*)b); }
 
 void fmmds_trim(void) {
   std::lock_guard<std::mutex> g(fmmds::g_cache_mu);

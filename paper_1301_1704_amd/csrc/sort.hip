@@ -124,15 +124,16 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 // one digit's run.
 // ---------------------------------------------------------------------------
 constexpr int kSortWaves = kSortBlock / 64;
-constexpr int kSortWSeg = 64 * kSortItems;
 
-template <bool PACKED>
+template <bool PACKED, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ vout, uint32_t n, uint32_t shift, const uint32_t* __restrict__ goff,
     uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter) {
-  __shared__ uint64_t s_key[kSortTile];
-  __shared__ uint32_t s_val[PACKED ? 1 : kSortTile];
+  constexpr int TILE = kSortBlock * ITEMS;
+  constexpr int WSEG = 64 * ITEMS;
+  __shared__ uint64_t s_key[TILE];
+  __shared__ uint32_t s_val[PACKED ? 1 : TILE];
   __shared__ uint32_t s_hist[kSortWaves][256];
   __shared__ uint32_t s_lstart[256];
   __shared__ uint32_t s_base[256];
@@ -144,19 +145,19 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   for (uint32_t i = tid; i < kSortWaves * 256; i += kSortBlock) (&s_hist[0][0])[i] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
-  const uint64_t wbase = (uint64_t)tile * kSortTile + (uint64_t)w * kSortWSeg;
+  const uint64_t wbase = (uint64_t)tile * TILE + (uint64_t)w * WSEG;
 
-  uint64_t k[kSortItems];
-  uint32_t v[kSortItems];
-  uint32_t r[kSortItems];
+  uint64_t k[ITEMS];
+  uint32_t v[ITEMS];
+  uint32_t r[ITEMS];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint64_t e = wbase + (uint64_t)i * 64 + lane;
     k[i] = e < n ? kin[e] : 0;
     if (!PACKED) v[i] = e < n ? vin[e] : 0;
   }
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const bool valid = wbase + (uint64_t)i * 64 + lane < n;
     const uint32_t d = (uint32_t)(k[i] >> shift) & 0xFFu;
     uint64_t peers = __ballot(valid);
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   __syncthreads();
 
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     if (wbase + (uint64_t)i * 64 + lane < n) {
       const uint32_t dd = (uint32_t)(k[i] >> shift) & 0xFFu;
       const uint32_t lp = s_lstart[dd] + s_hist[w][dd] + r[i];
@@ -205,8 +206,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     }
   }
   __syncthreads();
-  const uint64_t tbase = (uint64_t)tile * kSortTile;
-  const uint32_t tcount = (uint32_t)min((uint64_t)kSortTile, (uint64_t)n - tbase);
+  const uint64_t tbase = (uint64_t)tile * TILE;
+  const uint32_t tcount = (uint32_t)min((uint64_t)TILE, (uint64_t)n - tbase);
   for (uint32_t j = tid; j < tcount; j += kSortBlock) {
     const uint64_t kk = s_key[j];
     const uint32_t dd = (uint32_t)(kk >> shift) & 0xFFu;
@@ -216,16 +217,26 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   }
 }
 
+uint32_t sort_tiles(uint32_t n, int items) { return div_up(n, (uint64_t)kSortBlock * items); }
+
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
-                      uint64_t* status, uint32_t* tile_counter, hipStream_t s) {
-  const uint32_t grid = div_up(n, kSortTile);
-  if (packed)
-    hipLaunchKernelGGL(k_sort_pass<true>, dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin, vout,
-                       n, shift, goff, status, tile_counter);
-  else
-    hipLaunchKernelGGL(k_sort_pass<false>, dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin,
-                       vout, n, shift, goff, status, tile_counter);
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items) {
+  const uint32_t grid = sort_tiles(n, items);
+#define FMMDS_SORT(P, I)                                                                        \
+  hipLaunchKernelGGL((k_sort_pass<P, I>), dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin,  \
+                     vout, n, shift, goff, status, tile_counter)
+  if (items == 8) {
+    if (packed) FMMDS_SORT(true, 8);
+    else FMMDS_SORT(false, 8);
+  } else if (items == 12) {
+    if (packed) FMMDS_SORT(true, 12);
+    else FMMDS_SORT(false, 12);
+  } else {
+    if (packed) FMMDS_SORT(true, 16);
+    else FMMDS_SORT(false, 16);
+  }
+#undef FMMDS_SORT
 }
 
 }  // namespace fmmds

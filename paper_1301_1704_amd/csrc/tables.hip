@@ -44,12 +44,16 @@ __device__ __forceinline__ uint64_t tile_flags_prefix(uint32_t* s_cnt, uint64_t*
 // and RecvPermutationIdx) and compact the finest level's nonempty boxes: their
 // keys and bookmarks (Algorithm 3's NonEmptyIdx and Bookmark).
 // ---------------------------------------------------------------------------
+// With a batch (set_off != nullptr) the key carries the set id from bit
+// `set_shift` up and the permutation is written relative to the set's first
+// point.
 template <bool PACKED, typename KeyT>
 __global__ __launch_bounds__(kCompBlock) void k_leaf(
     const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv, const P3* __restrict__ xyz,
     uint32_t n, uint32_t* __restrict__ perm, P3* __restrict__ sorted_xyz,
     KeyT* __restrict__ leaf_key, uint32_t* __restrict__ leaf_begin, uint64_t* __restrict__ status,
-    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ n_out) {
+    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ n_out,
+    const uint64_t* __restrict__ set_off, uint32_t set_shift) {
   __shared__ uint32_t s_cnt[kCompItems * kCompWaves];
   __shared__ uint64_t s_excl;
   __shared__ uint32_t s_tile;
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(kCompBlock) void k_leaf(
       kk = PACKED ? (el >> 32) : el;
       idx = PACKED ? (uint32_t)el : sv[e];
       if (e > 0) kp = PACKED ? (sk[e - 1] >> 32) : sk[e - 1];
-      perm[e] = idx;
+      perm[e] = set_off ? idx - (uint32_t)set_off[kk >> set_shift] : idx;
       sorted_xyz[e] = xyz[idx];
     }
     const bool f = valid && (e == 0 || kk != kp);
@@ -102,12 +106,12 @@ __global__ __launch_bounds__(kCompBlock) void k_leaf(
 void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
                  const float* xyz, uint32_t n, uint32_t* perm, float* sorted_xyz, void* leaf_key,
                  uint32_t* leaf_begin, uint64_t* status, uint32_t* tile_counter, uint32_t* n_out,
-                 hipStream_t s) {
+                 hipStream_t s, const uint64_t* set_off, uint32_t set_shift) {
   const uint32_t grid = div_up(n, kCompTile);
 #define FMMDS_LEAF(P, K)                                                                         \
   hipLaunchKernelGGL((k_leaf<P, K>), dim3(grid), dim3(kCompBlock), 0, s, sk, sv, (const P3*)xyz, \
                      n, perm, (P3*)sorted_xyz, (K*)leaf_key, leaf_begin, status, tile_counter,    \
-                     n_out)
+                     n_out, set_off, set_shift)
   if (packed && key64) FMMDS_LEAF(true, uint64_t);
   else if (packed) FMMDS_LEAF(true, uint32_t);
   else if (key64) FMMDS_LEAF(false, uint64_t);
