@@ -71,6 +71,48 @@ def cpu_baseline(name: str):
             "cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
 
 
+def bench_batched(F, torch, args):
+    """Builds/sec of the batched form (512 sets of 2^10..2^20 points, one
+    graph-replayed launch sequence) against the same 512 sets built one by
+    one with fmmds_build on the same GPU and stream."""
+    from paper_1301_1704_amd import inputs as I
+    log("batched: generating 512 sets")
+    xyz, off, lev = I.batch_sets()
+    x = torch.from_numpy(xyz).cuda()
+    n_sets = len(lev)
+    b = F.Batch(off, lev)
+    for _ in range(2):  # capture (with tile autotuning), then a replay
+        b.launch(x, capture=True)
+        b.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        b.launch(x, capture=True)
+        b.wait()
+    dt_batch = (time.perf_counter() - t0) / args.batch_steps
+    items = b.sort_items
+    b.free()
+    sets = [x[int(off[i]):int(off[i + 1])] for i in range(n_sets)]
+    for i in range(0, n_sets, 16):  # warm the plain path (code, cache)
+        F.build(sets[i], None, max_level=int(lev[i]), key_bits=64).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_sets):
+        F.build(sets[i], None, max_level=int(lev[i]), key_bits=64).free()
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    res = {"workload": f"{n_sets} shared sets, 2^10..2^20 points (log-uniform), levels "
+                       f"{int(lev.min())}..{int(lev.max())}, uniform/clustered alternating",
+           "points": int(off[-1]), "sets": n_sets, "ms_per_batch": dt_batch * 1e3,
+           "builds_per_s": n_sets / dt_batch, "points_per_s": int(off[-1]) / dt_batch,
+           "plain_ms_all_sets": dt_plain * 1e3, "plain_builds_per_s": n_sets / dt_plain,
+           "speedup_vs_plain": dt_plain / dt_batch, "graph": True, "sort_items": items}
+    log(f"batched: {res['ms_per_batch']:.2f} ms per 512-set batch "
+        f"({res['builds_per_s']:.0f} builds/s) vs plain {res['plain_ms_all_sets']:.1f} ms "
+        f"({res['plain_builds_per_s']:.0f} builds/s)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +120,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform", choices=["uniform", "nonuniform", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event timing (no roofline object)")
     args = ap.parse_args()
@@ -167,6 +211,8 @@ def main():
                                "avg_us": round(1e3 * b["total_ms"] / b["launches"], 2),
                                "GBps": round(b["bytes"] / (b["total_ms"] * 1e6), 1)}
                            for k, b in breakdown.items()}
+    if not args.no_batch:
+        line["batched"] = bench_batched(F, torch, args)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample")
         line["cpu_baseline"] = cpu_baseline(args.workload)
