@@ -17,6 +17,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -113,6 +115,51 @@ def bench_batched(F, torch, args):
     return res
 
 
+def bench_serving(F, torch, args):
+    """Continuous-batching serving of rebuild requests from 64 moving particle
+    systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
+    the saturated one-at-a-time build rate of the same mix, against the
+    one-at-a-time loop replaying the identical arrival trace."""
+    from paper_1301_1704_amd import inputs as I
+    from paper_1301_1704_amd import serving as S
+    log("serving: generating 64 systems")
+    systems, levels = I.serving_systems()
+    xs = [torch.from_numpy(p).cuda() for p in systems]
+    for i in range(0, 64, 8):
+        F.build(xs[i], None, max_level=levels[i], key_bits=64).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, lv in zip(xs, levels):
+        F.build(x, None, max_level=lv, key_bits=64).free()
+    torch.cuda.synchronize()
+    sat = len(xs) / (time.perf_counter() - t0)
+    del xs
+    rate = 0.7 * sat
+    n_req = args.serving_warmup + args.serving_requests
+    arr, pick = I.poisson_trace(n_req, rate, len(systems))
+    srv = S.Server(systems, levels, n_slots=4)
+    reqs = srv.run(arr, pick)
+    evict = srv.evictions
+    srv.close()
+    ours = S.latency_stats(reqs, skip=args.serving_warmup)
+    batch_sizes = {}
+    for r in reqs[args.serving_warmup:]:
+        batch_sizes[r.launched] = batch_sizes.get(r.launched, 0) + 1
+    seq = S.latency_stats(S.run_sequential(systems, levels, arr, pick), skip=args.serving_warmup)
+    res = {"workload": "64 systems, 2^14..2^22 points (log-uniform), 64-cluster Gaussian, "
+                       "levels 3..6, N(0, 1e-3) displacement per step",
+           "arrival_rate_per_s": rate, "saturated_plain_rate_per_s": sat,
+           "warmup_requests": args.serving_warmup, **ours, "slots": 4,
+           "mean_requests_per_batch": float(np.mean(list(batch_sizes.values()))),
+           "evictions": evict,
+           "plain_sequential": seq,
+           "p99_vs_plain": seq["p99_ms"] / ours["p99_ms"] if ours["p99_ms"] > 0 else None}
+    log(f"serving: p50 {ours['p50_ms']:.2f} ms p99 {ours['p99_ms']:.2f} ms "
+        f"{ours['builds_per_s']:.0f} builds/s; one-at-a-time p50 {seq['p50_ms']:.2f} ms "
+        f"p99 {seq['p99_ms']:.2f} ms {seq['builds_per_s']:.0f} builds/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +168,9 @@ def main():
     ap.add_argument("--workload", default="uniform", choices=["uniform", "nonuniform", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event timing (no roofline object)")
@@ -130,7 +180,6 @@ def main():
               "(independent point sets shard trivially, one set spans one GPU)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
     import torch
     import paper_1301_1704_amd as F
 
@@ -213,6 +262,8 @@ def main():
                            for k, b in breakdown.items()}
     if not args.no_batch:
         line["batched"] = bench_batched(F, torch, args)
+    if not args.no_serving:
+        line["serving"] = bench_serving(F, torch, args)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a sample")
         line["cpu_baseline"] = cpu_baseline(args.workload)

@@ -182,6 +182,12 @@ fmmds_status fmmds_batch_create(const uint64_t* set_offsets, const uint8_t* leve
 fmmds_status fmmds_batch_launch(fmmds_batch* b, const float* xyz, int capture);
 fmmds_status fmmds_batch_wait(fmmds_batch* b);
 const fmmds_tree* fmmds_batch_tree(const fmmds_batch* b, uint32_t set);
+/* Device bytes a batch of this shape allocates (host only, no device work):
+ * for admission by memory footprint before fmmds_batch_create. */
+fmmds_status fmmds_batch_footprint(const uint64_t* set_offsets, const uint8_t* levels,
+                                   uint32_t n_sets, uint64_t* bytes);
+/* Device bytes the batch holds. */
+uint64_t fmmds_batch_bytes(const fmmds_batch* b);
 /* Sort tile size (elements per thread: 8, 12 or 16) the batch uses. */
 uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
 void fmmds_batch_free(fmmds_batch* b);

@@ -89,6 +89,10 @@ def _lib():
         L.fmmds_batch_wait.restype = C.c_int
         L.fmmds_batch_tree.argtypes = [_vp, _u32]
         L.fmmds_batch_tree.restype = C.POINTER(TreeStruct)
+        L.fmmds_batch_footprint.argtypes = [_vp, _vp, _u32, C.POINTER(_u64)]
+        L.fmmds_batch_footprint.restype = C.c_int
+        L.fmmds_batch_bytes.argtypes = [_vp]
+        L.fmmds_batch_bytes.restype = _u64
         L.fmmds_batch_sort_items.argtypes = [_vp]
         L.fmmds_batch_sort_items.restype = _u32
         L.fmmds_batch_free.argtypes = [_vp]
@@ -114,7 +118,20 @@ def exported_symbols():
             "fmmds_trim", "fmmds_profile_enable", "fmmds_profile_reset",
             "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
-            "fmmds_batch_sort_items", "fmmds_batch_free"]
+            "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
+            "fmmds_batch_free"]
+
+
+def batch_footprint(set_offsets, levels) -> int:
+    """Device bytes a batch of this shape would allocate (host only)."""
+    off = np.ascontiguousarray(set_offsets, dtype=np.uint64)
+    lev = np.ascontiguousarray(levels, dtype=np.uint8)
+    out = _u64()
+    st = _lib().fmmds_batch_footprint(off.ctypes.data_as(_vp), lev.ctypes.data_as(_vp),
+                                      int(lev.size), C.byref(out))
+    if st != OK:
+        raise FmmdsError(st, "fmmds_batch_footprint")
+    return int(out.value)
 
 
 def trim():
@@ -372,6 +389,10 @@ class Batch:
         if not t:
             raise RuntimeError("no tree: launch and wait first")
         return Tree(t, owner=self)
+
+    @property
+    def nbytes(self) -> int:
+        return int(_lib().fmmds_batch_bytes(self._h))
 
     @property
     def sort_items(self) -> int:

@@ -15,6 +15,7 @@
 #include <tuple>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -45,11 +46,32 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // order protects it); another stream first waits on an event recorded on S at
 // release time. fmmds_trim returns every cached block to HIP.
 // ---------------------------------------------------------------------------
+// An event shared by the blocks released together; destroyed with the last.
+struct SharedEvent {
+  hipEvent_t ev = nullptr;
+  ~SharedEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+using EventRef = std::shared_ptr<SharedEvent>;
+
+EventRef record_event(hipStream_t stream) {
+  EventRef e = std::make_shared<SharedEvent>();
+  if (hipEventCreateWithFlags(&e->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(e->ev, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(stream);  // no event: make the block safe now
+    if (e->ev) (void)hipEventDestroy(e->ev);
+    e->ev = nullptr;
+  }
+  return e;
+}
+
 struct CachedBlock {
   void* p;
   size_t bytes;
   hipStream_t stream;
-  hipEvent_t ready;  // recorded on `stream` at release
+  EventRef ready;  // completes when the releasing stream is done with the block
 };
 std::mutex g_cache_mu;
 std::map<int, std::multimap<size_t, CachedBlock>> g_cache;  // device -> size -> block
@@ -79,8 +101,8 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
     if (best != m.end()) {
       CachedBlock b = best->second;
       m.erase(best);
-      if (b.stream != stream) ck(hipStreamWaitEvent(stream, b.ready, 0));
-      (void)hipEventDestroy(b.ready);
+      if (b.stream != stream && b.ready && b.ready->ev)
+        ck(hipStreamWaitEvent(stream, b.ready->ev, 0));
       g_live[b.p] = b.bytes;
       return b.p;
     }
@@ -93,10 +115,7 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
     auto& m = g_cache[dev];
     if (!m.empty()) {
       (void)hipDeviceSynchronize();
-      for (auto& kv : m) {
-        (void)hipFree(kv.second.p);
-        (void)hipEventDestroy(kv.second.ready);
-      }
+      for (auto& kv : m) (void)hipFree(kv.second.p);
       m.clear();
       if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -110,23 +129,55 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
   return p;
 }
 
-void cache_release(void* p, hipStream_t stream) {
+// `ready` (optional) completes when all work using the block is done; without
+// it an event is recorded on `stream` now.
+void cache_release(void* p, hipStream_t stream, EventRef ready = nullptr) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
-  hipEvent_t ev = nullptr;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(ev, stream) != hipSuccess) {
-    (void)hipGetLastError();
-    if (ev) (void)hipEventDestroy(ev);
-    (void)hipStreamSynchronize(stream);
-    ev = nullptr;
-    (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  }
+  if (!ready) ready = record_event(stream);
   std::lock_guard<std::mutex> g(g_cache_mu);
   auto it = g_live.find(p);
   if (it == g_live.end()) return;
-  g_cache[dev].insert({it->second, CachedBlock{p, it->second, stream, ev}});
+  g_cache[dev].insert({it->second, CachedBlock{p, it->second, stream, ready}});
   g_live.erase(it);
+}
+
+// Pinned host blocks (batch metadata mirrors), cached the same way; a block
+// is reused only once the device work that writes it has completed.
+struct PinnedBlock {
+  void* p;
+  EventRef ready;
+};
+std::multimap<size_t, PinnedBlock> g_pinned_free;
+
+void* pinned_alloc(size_t bytes) {
+  bytes = round_up(bytes, 4096);
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (auto it = g_pinned_free.lower_bound(bytes);
+         it != g_pinned_free.end() && it->first - bytes <= it->first / 8; ++it) {
+      if (it->second.ready && it->second.ready->ev &&
+          hipEventQuery(it->second.ready->ev) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      void* p = it->second.p;
+      g_pinned_free.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pinned_release(void* p, size_t bytes, EventRef ready) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  g_pinned_free.insert({round_up(bytes, 4096), PinnedBlock{p, ready}});
 }
 
 // Device memory through the caller's allocator, or the library's cache.
@@ -142,11 +193,11 @@ struct Allocator {
     if (!p) throw Fail{FMMDS_ERR_NOMEM};
     return p;
   }
-  void put(void* p, size_t bytes) {
+  void put(void* p, size_t bytes, const EventRef& ready = nullptr) {
     if (!p) return;
     bytes = round_up(std::max<size_t>(bytes, 1), 256);
     if (release) release(ctx, p, bytes, (void*)stream);
-    else cache_release(p, stream);
+    else cache_release(p, stream, ready);
   }
 };
 
@@ -166,8 +217,10 @@ struct Pool {
     blocks.push_back({p, bytes});
     return (T*)p;
   }
-  void release_all() {
-    for (auto it = blocks.rbegin(); it != blocks.rend(); ++it) A->put(it->p, it->bytes);
+  void release_all(const EventRef& ready = nullptr) {
+    EventRef ev = ready;
+    if (!ev && !A->release && !blocks.empty()) ev = record_event(A->stream);  // one for all
+    for (auto it = blocks.rbegin(); it != blocks.rend(); ++it) A->put(it->p, it->bytes, ev);
     blocks.clear();
   }
 };
@@ -674,7 +727,8 @@ struct BatchImpl {
   // device block copied back after each launch: DevMeta, first, bases
   char* dblock = nullptr;
   size_t dblock_b = 0, first_at = 0, base_at = 0;
-  char* hblock = nullptr;  // pinned mirror
+  char* hblock = nullptr;  // pinned mirror, followed by the staged offsets and levels
+  size_t hblock_b = 0;
   // zeroed per launch: dblock, histograms, digit offsets, tickets, status words
   char* ws = nullptr;
   size_t ws_b = 0, hist_at = 0, goffd_at = 0, tick_at = 0, words_at = 0;
@@ -683,6 +737,8 @@ struct BatchImpl {
   hipGraphExec_t exec = nullptr;
   const float* graph_xyz = nullptr;
   bool launched = false;
+  size_t footprint = 0;  // device bytes of the plan
+  EventRef done;         // recorded after the last launch's work
   std::vector<fmmds_tree> trees;
   std::vector<TreeImpl> views;
 
@@ -908,8 +964,6 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
     Pool& M = B->mem;
     B->d_off = M.get<uint64_t>(n_sets + 1);
     B->d_lev = M.get<uint8_t>(n_sets);
-    ck(hipMemcpyAsync(B->d_off, set_offsets, (n_sets + 1) * 8, hipMemcpyHostToDevice, B->stream));
-    ck(hipMemcpyAsync(B->d_lev, levels, n_sets, hipMemcpyHostToDevice, B->stream));
     B->sb.k[0] = M.get<uint64_t>(P);
     B->sb.k[1] = M.get<uint64_t>(P);
     if (!B->packed) {
@@ -960,16 +1014,24 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
     B->ws_b = round_up(B->words_at + words * 8, 256);
     B->ws = M.get<char>(B->ws_b);
     B->dblock = B->ws;
-    void* hp = nullptr;
-    if (hipHostMalloc(&hp, B->dblock_b, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Fail{FMMDS_ERR_NOMEM};
-    }
-    B->hblock = (char*)hp;
+    // Pinned host block: the metadata mirror, then the offsets and levels
+    // staged for an asynchronous upload (it lives as long as the batch).
+    const size_t stage_off = round_up(B->dblock_b, 256);
+    const size_t stage_lev = stage_off + round_up((n_sets + 1) * 8, 256);
+    B->hblock_b = stage_lev + n_sets;
+    B->hblock = (char*)pinned_alloc(B->hblock_b);
+    if (!B->hblock) throw Fail{FMMDS_ERR_NOMEM};
+    std::memcpy(B->hblock + stage_off, set_offsets, (n_sets + 1) * 8);
+    std::memcpy(B->hblock + stage_lev, levels, n_sets);
+    ck(hipMemcpyAsync(B->d_off, B->hblock + stage_off, (n_sets + 1) * 8, hipMemcpyHostToDevice,
+                      B->stream));
+    ck(hipMemcpyAsync(B->d_lev, B->hblock + stage_lev, n_sets, hipMemcpyHostToDevice, B->stream));
     B->trees.assign(n_sets, fmmds_tree());
     B->views.resize(n_sets);
     for (uint32_t i = 0; i < n_sets; ++i) B->views[i].view = true;
-    ck(hipStreamSynchronize(B->stream));
+    B->footprint = 0;
+    for (const Block& blk : M.blocks)
+      B->footprint += cache_round(round_up(std::max<size_t>(blk.bytes, 1), 256));
   } catch (const Fail& f) {
     result = f.st;
   } catch (const std::bad_alloc&) {
@@ -978,12 +1040,68 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
   if (result != FMMDS_OK) {
     (void)hipGetLastError();
     B->mem.release_all();
-    if (B->hblock) (void)hipHostFree(B->hblock);
+    if (B->hblock) {
+      (void)hipStreamSynchronize(B->stream);
+      pinned_release(B->hblock, B->hblock_b, nullptr);
+    }
     if (B->own_stream) (void)hipStreamDestroy(B->stream);
     delete B;
     return result;
   }
   *out = (fmmds_batch*)B;
+  return FMMDS_OK;
+}
+
+// Device bytes fmmds_batch_create would allocate for this shape (host only;
+// mirrors the allocations of batch_create, each rounded as the allocator does).
+fmmds_status batch_footprint(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
+                             uint64_t* bytes) {
+  if (!set_offsets || !levels || !bytes || n_sets == 0 || set_offsets[0] != 0)
+    return FMMDS_ERR_ARG;
+  uint32_t L = 0;
+  for (uint32_t i = 0; i < n_sets; ++i) {
+    if (set_offsets[i + 1] <= set_offsets[i] || levels[i] < 2 || levels[i] > FMMDS_MAX_LEVEL)
+      return FMMDS_ERR_ARG;
+    L = std::max<uint32_t>(L, levels[i]);
+  }
+  if (set_offsets[n_sets] >= 0xFFFFFFFFull) return FMMDS_ERR_ARG;
+  uint32_t setbits = 1;
+  while ((1ull << setbits) < n_sets) ++setbits;
+  if (setbits + 3 * L > 64) return FMMDS_ERR_ARG;
+  const uint64_t P = set_offsets[n_sets];
+  const bool packed = setbits + 3 * L <= 32;
+  const uint32_t n_pass = div_up(setbits + 3 * L, 8);
+  auto blk = [](uint64_t b) { return (uint64_t)cache_round(round_up(std::max<uint64_t>(b, 1), 256)); };
+  uint64_t total = blk((n_sets + 1) * 8) + blk(n_sets) + 2 * blk(8 * P) +
+                   (packed ? 0 : 2 * blk(4 * P)) + blk(4 * P) + blk(12 * P);
+  uint64_t cmax = 0, words = (uint64_t)n_pass * sort_tiles((uint32_t)P, 8) * 256 +
+                            div_up(P, kCompTile);
+  for (uint32_t l = 0; l <= L; ++l) {
+    uint64_t c = 0, r = 0;
+    for (uint32_t i = 0; i < n_sets; ++i) {
+      const uint64_t ni = set_offsets[i + 1] - set_offsets[i];
+      const uint64_t boxes = std::min<uint64_t>(ni, 1ull << (3 * std::min<uint32_t>(l, levels[i])));
+      c += boxes;
+      if (levels[i] >= l) r += boxes;
+    }
+    cmax = std::max(cmax, c);
+    total += blk(8 * c) + blk(4 * (c + 1)) + blk(8 * c) + blk(4 * (c + n_sets));
+    if (l >= 1) total += blk(4 * c) + blk(4 * c);
+    if (l < L) total += blk(4 * (c + 1)) + blk(c) + blk(4 * (c + n_sets));
+    if (l >= 2) total += 2 * (blk(4 * (c + 1)) + blk(4 * (c + n_sets))) + blk(4 * 27 * r) +
+                         blk(4 * 189 * r);
+    if (l >= 1) words += div_up(c, kCompTile);  // level l-1 from level l
+    if (l >= 2) words += 2 * (uint64_t)div_up(c, kCompTile);
+  }
+  total += blk(2 * 4 * std::max<uint64_t>(cmax, 1));
+  const uint64_t dblock = round_up(round_up(round_up(sizeof(DevMeta), 256) +
+                                            (uint64_t)(L + 1) * (n_sets + 1) * 4, 256) +
+                                       (uint64_t)(L + 1) * 2 * (n_sets + 1) * 4,
+                                   256);
+  const uint64_t tickets = n_pass + 1 + L + 2 * (L + 1);
+  total += blk(dblock + 2 * round_up(kMaxPasses * 256 * 4, 256) + round_up(tickets * 4, 256) +
+               words * 8);
+  *bytes = total;
   return FMMDS_OK;
 }
 
@@ -1023,6 +1141,7 @@ fmmds_status batch_launch(BatchImpl* B, const float* xyz, int capture) {
       batch_enqueue(*B, xyz, P);
       P.finish([](const Prof::Rec&) { return 0.0; });
     }
+    B->done = record_event(B->stream);
     B->launched = true;
   } catch (const Fail& f) {
     (void)hipGetLastError();
@@ -1082,17 +1201,16 @@ fmmds_status batch_wait(BatchImpl* B) {
   return FMMDS_OK;
 }
 
+// No host wait: the blocks go back to the caches tagged with the event of
+// the batch's last launch (or of its creation's uploads).
 void batch_free(BatchImpl* B) {
   if (!B) return;
-  (void)hipStreamSynchronize(B->stream);
+  EventRef ready = B->done ? B->done : record_event(B->stream);
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
-  B->mem.release_all();
-  if (B->hblock) (void)hipHostFree(B->hblock);
-  if (B->own_stream) {
-    (void)hipStreamSynchronize(B->stream);
-    (void)hipStreamDestroy(B->stream);
-  }
+  B->mem.release_all(ready);
+  pinned_release(B->hblock, B->hblock_b, ready);
+  if (B->own_stream) (void)hipStreamDestroy(B->stream);  // returns once its work is queued
   delete B;
 }
 
@@ -1165,6 +1283,15 @@ const fmmds_tree* fmmds_batch_tree(const fmmds_batch* b, uint32_t set) {
   return &B->trees[set];
 }
 
+fmmds_status fmmds_batch_footprint(const uint64_t* set_offsets, const uint8_t* levels,
+                                   uint32_t n_sets, uint64_t* bytes) {
+  return fmmds::batch_footprint(set_offsets, levels, n_sets, bytes);
+}
+
+uint64_t fmmds_batch_bytes(const fmmds_batch* b) {
+  return b ? ((const fmmds::BatchImpl*)b)->footprint : 0;
+}
+
 uint32_t fmmds_batch_sort_items(const fmmds_batch* b) {
   return b ? (uint32_t)((const fmmds::BatchImpl*)b)->items : 0;
 }
@@ -1181,10 +1308,7 @@ void fmmds_trim(void) {
   (void)hipDeviceSynchronize();
   for (auto& d : fmmds::g_cache) {
     (void)hipSetDevice(d.first);
-    for (auto& kv : d.second) {
-      (void)hipFree(kv.second.p);
-      (void)hipEventDestroy(kv.second.ready);
-    }
+    for (auto& kv : d.second) (void)hipFree(kv.second.p);
     d.second.clear();
   }
   (void)hipSetDevice(dev);

@@ -205,3 +205,31 @@ def batch_sets(n_sets: int = 512, seed: int = 7, lo_log2: int = 10, hi_log2: int
     off[1:] = np.cumsum(sizes).astype(np.uint64)
     return (np.ascontiguousarray(np.concatenate(parts, axis=0)), off,
             np.asarray(levels, dtype=np.uint8))
+
+
+def serving_systems(n_systems: int = 64, seed: int = 8, lo_log2: int = 14, hi_log2: int = 22):
+    """Particle systems of the serving workload: sizes floor(2^(lo + (hi - lo) U)),
+    64 Gaussian clusters each (sigma 0.01, own centres), level
+    ceil(log8(n / 64)). Returns (list of FP32 [n, 3] arrays, levels)."""
+    u = uniform53(stream_seed(seed, TAG_SIZES), n_systems)
+    sizes = np.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)).astype(np.int64)
+    pts, levels = [], []
+    for i, n in enumerate(sizes):
+        s = stream_seed(seed, 0x200 + i)
+        pts.append(cluster_points(s, int(n), cluster_centres(s, 64), 0.01))
+        levels.append(level_for_size(int(n)))
+    return pts, levels
+
+
+def poisson_trace(n_requests: int, rate: float, n_systems: int, seed: int = 8):
+    """Arrival times (seconds, from 0) of a Poisson process of the given rate
+    and the system each request rebuilds (uniform)."""
+    u = uniform53(stream_seed(seed, TAG_ARRIVAL), n_requests)
+    gaps = -np.log(1.0 - u) / rate
+    pick = splitmix64(stream_seed(seed, TAG_PICK), n_requests) % np.uint64(n_systems)
+    return np.cumsum(gaps), pick.astype(np.int64)
+
+
+def displacement_seed(seed: int, system: int, step: int) -> int:
+    """Seed of the N(0, sigma^2) displacement of one system at one step."""
+    return stream_seed(seed, TAG_STEP, system, step) & 0x7FFFFFFFFFFFFFFF

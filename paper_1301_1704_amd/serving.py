@@ -1,0 +1,315 @@
+"""Serving loop: continuous batching of rebuild requests for moving particle
+systems.
+
+The paper motivates fast data-structure construction by dynamic problems in
+which particles move every time step and the structures are rebuilt each step
+(Section 1, Section 2.5). This module serves a stream of such rebuild requests
+on one GPU:
+
+- every request names a system; it displaces the system's points by
+  N(0, sigma^2) per coordinate (seeded by system and step, clamped into the
+  unit cube) and rebuilds its tables and lists;
+- requests wait in arrival order; whenever one of `n_slots` streams is free,
+  the waiting requests (at most one per system, since a system's steps are
+  sequential) are packed into one batched build (fmmds_batch_*) and launched
+  on that stream, so work from different ticks overlaps on the device;
+- a batch is admitted only if its device footprint (fmmds_batch_footprint)
+  fits the HBM budget next to everything still resident; if nothing is in
+  flight and even one request does not fit, the oldest resident tables are
+  evicted (their systems are rebuilt from scratch on their next request);
+  a request that does not fit an empty budget fails with ERR_NOMEM;
+- each system keeps its latest tables resident on the GPU (a view into the
+  batch that built them); a batch is released once none of its systems still
+  points at it.
+
+All compute is the library's; this is host scheduling only. The sequential
+baseline replays the same arrival trace with one fmmds_build per request on
+one stream.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+
+ONE_MINUS_ULP = 1.0 - 2.0 ** -24
+
+
+@dataclass
+class Request:
+    rid: int
+    system: int
+    arrival: float
+    step: int = -1
+    launched: float = -1.0
+    done: float = -1.0
+
+
+@dataclass
+class _Live:
+    batch: object
+    refs: int
+    nbytes: int
+
+
+@dataclass
+class _Slot:
+    stream: object
+    batch: object = None
+    event: object = None
+    reqs: list = field(default_factory=list)
+    xbuf: object = None
+
+
+class Server:
+    def __init__(self, systems, levels, *, n_slots: int = 4, hbm_budget: int | None = None,
+                 max_batch_points: int = 1 << 24, max_batch_sets: int = 64,
+                 sigma: float = 1e-3, seed: int = 8, keep_inputs=(),
+                 stall_seconds: float = 60.0):
+        import torch
+        import paper_1301_1704_amd as F
+        self.torch, self.F = torch, F
+        self.levels = [int(v) for v in levels]
+        self.x0 = [np.ascontiguousarray(p, dtype=np.float32) for p in systems]
+        self.n = [p.shape[0] for p in self.x0]
+        self.sigma, self.seed = sigma, seed
+        self.max_batch_points, self.max_batch_sets = max_batch_points, max_batch_sets
+        self.slots = [_Slot(stream=torch.cuda.Stream()) for _ in range(n_slots)]
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.5 * free)
+        self.budget = hbm_budget
+        self.keep_inputs = set(keep_inputs)  # request ids whose inputs are kept (tests)
+        self.stall_seconds = stall_seconds
+        self.reset()
+
+    # ------------------------------------------------------------- state
+    def reset(self):
+        torch = self.torch
+        torch.cuda.synchronize()
+        self.x = [torch.from_numpy(p).cuda() for p in self.x0]
+        self.step = [0] * len(self.x0)
+        self.latest = [None] * len(self.x0)     # (live id, set index) of resident tables
+        self.live = {}                          # live id -> _Live
+        self.resident = 0
+        self.next_live = 0
+        self.kept_inputs = {}
+        self.results = {}                       # rid -> (live id, set index) while resident
+        self.evictions = 0
+        torch.cuda.synchronize()
+
+    def _displace(self, s: int, stream):
+        torch = self.torch
+        g = torch.Generator(device="cuda")
+        g.manual_seed(I.displacement_seed(self.seed, s, self.step[s]))
+        with torch.cuda.stream(stream):
+            noise = torch.randn(self.x[s].shape, generator=g, device="cuda")
+            self.x[s].add_(noise, alpha=self.sigma).clamp_(0.0, ONE_MINUS_ULP)
+        self.step[s] += 1
+
+    def _release(self, lid):
+        e = self.live[lid]
+        e.refs -= 1
+        if e.refs == 0:
+            e.batch.free()
+            self.resident -= e.nbytes
+            del self.live[lid]
+
+    def _evict_oldest(self) -> bool:
+        """Drop the oldest resident batch (all its systems lose their resident
+        tables until their next rebuild). Only called with nothing in flight."""
+        if not self.live:
+            return False
+        lid = min(self.live)
+        e = self.live.pop(lid)
+        for s, v in enumerate(self.latest):
+            if v is not None and v[0] == lid:
+                self.latest[s] = None
+        e.batch.free()
+        self.resident -= e.nbytes
+        self.evictions += 1
+        return True
+
+    # ------------------------------------------------------------- batches
+    def _launch(self, slot: _Slot, reqs: list, now: float):
+        torch, F = self.torch, self.F
+        sizes = [self.n[r.system] for r in reqs]
+        off = np.zeros(len(reqs) + 1, dtype=np.uint64)
+        off[1:] = np.cumsum(sizes)
+        lev = np.asarray([self.levels[r.system] for r in reqs], dtype=np.uint8)
+        b = F.Batch(off, lev, stream=slot.stream)
+        with torch.cuda.stream(slot.stream):
+            slot.xbuf = torch.empty((int(off[-1]), 3), dtype=torch.float32, device="cuda")
+        for i, r in enumerate(reqs):
+            r.step = self.step[r.system]
+            self._displace(r.system, slot.stream)
+            with torch.cuda.stream(slot.stream):
+                slot.xbuf[int(off[i]):int(off[i + 1])].copy_(self.x[r.system])
+                if r.rid in self.keep_inputs:
+                    self.kept_inputs[r.rid] = self.x[r.system].clone()
+            r.launched = now
+        b.launch(slot.xbuf)
+        ev = torch.cuda.Event()
+        ev.record(slot.stream)
+        slot.batch, slot.event, slot.reqs = b, ev, reqs
+        lid = self.next_live
+        self.next_live += 1
+        self.live[lid] = _Live(b, len(reqs), b.nbytes)
+        self.resident += b.nbytes
+        slot.lid = lid
+
+    def _finish(self, slot: _Slot, t0: float):
+        slot.batch.wait()
+        done = time.perf_counter() - t0
+        lid = slot.lid
+        for i, r in enumerate(slot.reqs):
+            r.done = done
+            old = self.latest[r.system]
+            self.latest[r.system] = (lid, i)
+            self.results[r.rid] = (lid, i)
+            if old is not None:
+                self._release(old[0])
+        slot.batch, slot.event, slot.reqs, slot.xbuf = None, None, [], None
+
+    def tree_of(self, rid: int):
+        """The tree a request produced, while it is still resident."""
+        lid, i = self.results[rid]
+        if lid not in self.live:
+            raise KeyError("tables of this request were replaced")
+        return self.live[lid].batch.tree(i)
+
+    # ------------------------------------------------------------- loop
+    def run(self, arrivals, systems, *, on_complete=None):
+        """Serve requests arriving at `arrivals` (seconds from the start) for
+        `systems`. Returns the list of Requests with launch and done times."""
+        reqs = [Request(i, int(s), float(a)) for i, (a, s) in enumerate(zip(arrivals, systems))]
+        pending = deque()
+        nxt = 0
+        busy = set()           # systems with a build in flight
+        t0 = time.perf_counter()
+        n_done = 0
+        last_progress = t0
+        while n_done < len(reqs):
+            now = time.perf_counter() - t0
+            if time.perf_counter() - last_progress > self.stall_seconds:
+                raise RuntimeError(f"serving loop made no progress for {self.stall_seconds} s "
+                                   f"({n_done}/{len(reqs)} done, {len(pending)} pending)")
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                pending.append(reqs[nxt])
+                nxt += 1
+            progressed = False
+            for slot in self.slots:
+                if slot.batch is not None and slot.event.query():
+                    fin = slot.reqs
+                    self._finish(slot, t0)
+                    for r in fin:
+                        busy.discard(r.system)
+                        if on_complete is not None:
+                            on_complete(self, r)
+                    n_done += len(fin)
+                    progressed = True
+            for slot in self.slots:
+                if slot.batch is not None or not pending:
+                    continue
+                take, pts, seen = [], 0, set()
+                for r in pending:
+                    if r.system in busy or r.system in seen:
+                        continue
+                    if take and (pts + self.n[r.system] > self.max_batch_points or
+                                 len(take) >= self.max_batch_sets):
+                        break
+                    take.append(r)
+                    seen.add(r.system)
+                    pts += self.n[r.system]
+                if not take:
+                    break
+                off = np.zeros(len(take) + 1, dtype=np.uint64)
+                off[1:] = np.cumsum([self.n[r.system] for r in take])
+                lev = np.asarray([self.levels[r.system] for r in take], dtype=np.uint8)
+                need = self.F.batch_footprint(off, lev)
+                while len(take) > 1 and self.resident + need > self.budget:
+                    take.pop()  # admit fewer
+                    off = off[:len(take) + 1]
+                    lev = lev[:len(take)]
+                    need = self.F.batch_footprint(off, lev)
+                if self.resident + need > self.budget:
+                    if any(sl.batch is not None for sl in self.slots):
+                        break  # wait: a completion will free memory
+                    # Nothing in flight: only evicting resident tables can make room.
+                    while self.resident + need > self.budget and self._evict_oldest():
+                        pass
+                    if self.resident + need > self.budget:
+                        raise self.F.FmmdsError(self.F.ERR_NOMEM,
+                                                f"request {take[0].rid} needs {need} bytes, "
+                                                f"budget {self.budget}")
+                for r in take:
+                    pending.remove(r)
+                    busy.add(r.system)
+                self._launch(slot, take, time.perf_counter() - t0)
+                progressed = True
+            if progressed or (nxt < len(reqs) and not pending):
+                last_progress = time.perf_counter()
+            if not progressed:
+                if nxt < len(reqs) and not pending and all(s.batch is None for s in self.slots):
+                    wait = reqs[nxt].arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.001))
+                else:
+                    time.sleep(0)
+        return reqs
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        for slot in self.slots:
+            if slot.batch is not None:
+                slot.batch.wait()
+        for e in list(self.live.values()):
+            e.batch.free()
+        self.live.clear()
+        self.resident = 0
+
+
+def run_sequential(systems, levels, arrivals, picks, *, sigma=1e-3, seed=8):
+    """Baseline: the same trace served one request at a time with fmmds_build
+    on one stream. Returns the list of Requests."""
+    import torch
+    import paper_1301_1704_amd as F
+    x = [torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda() for p in systems]
+    step = [0] * len(x)
+    latest = [None] * len(x)
+    reqs = [Request(i, int(s), float(a)) for i, (a, s) in enumerate(zip(arrivals, picks))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival:
+            pass
+        r.launched = time.perf_counter() - t0
+        g = torch.Generator(device="cuda")
+        g.manual_seed(I.displacement_seed(seed, r.system, step[r.system]))
+        r.step = step[r.system]
+        noise = torch.randn(x[r.system].shape, generator=g, device="cuda")
+        x[r.system].add_(noise, alpha=sigma).clamp_(0.0, ONE_MINUS_ULP)
+        step[r.system] += 1
+        t = F.build(x[r.system], None, max_level=int(levels[r.system]), key_bits=64)
+        torch.cuda.synchronize()
+        r.done = time.perf_counter() - t0
+        if latest[r.system] is not None:
+            latest[r.system].free()
+        latest[r.system] = t
+    for t in latest:
+        if t is not None:
+            t.free()
+    return reqs
+
+
+def latency_stats(reqs, skip: int = 0) -> dict:
+    rs = reqs[skip:]
+    lat = np.asarray([r.done - r.arrival for r in rs]) * 1e3
+    span = max(r.done for r in rs) - min(r.arrival for r in rs)
+    return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "builds_per_s": len(rs) / span if span > 0 else float("nan")}

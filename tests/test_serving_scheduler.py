@@ -1,0 +1,160 @@
+"""Host logic of the serving loop, on the CPU: with stand-ins for the GPU
+library (a batch's footprint is 10 bytes per point, every launch completes at
+once), the scheduler serves every request, keeps resident memory within the
+budget, evicts under pressure instead of stalling, and rejects a request that
+cannot fit an empty budget."""
+import numpy as np
+import pytest
+
+import paper_1301_1704_amd.serving as S
+
+
+class _Batch:
+    def __init__(self, off, lev, stream=None):
+        self.nbytes = int(off[-1]) * 10
+        self.freed = False
+
+    def launch(self, x):
+        pass
+
+    def wait(self):
+        pass
+
+    def free(self):
+        assert not self.freed
+        self.freed = True
+
+    def tree(self, i):
+        return ("tree", i)
+
+
+class _Event:
+    def record(self, stream):
+        pass
+
+    def query(self):
+        return True
+
+
+class _Tensor:
+    shape = (1, 3)
+
+    def cuda(self):
+        return self
+
+    def add_(self, *a, **k):
+        return self
+
+    def clamp_(self, *a):
+        return self
+
+    def clone(self):
+        return self
+
+    def __getitem__(self, k):
+        return self
+
+    def copy_(self, o):
+        return self
+
+
+class _Ctx:
+    def __enter__(self):
+        pass
+
+    def __exit__(self, *a):
+        pass
+
+
+class _Torch:
+    float32 = None
+
+    class cuda:
+        Event = _Event
+
+        @staticmethod
+        def synchronize():
+            pass
+
+        @staticmethod
+        def stream(s):
+            return _Ctx()
+
+    @staticmethod
+    def from_numpy(x):
+        return _Tensor()
+
+    @staticmethod
+    def empty(*a, **k):
+        return _Tensor()
+
+
+class _Lib:
+    Batch = _Batch
+    ERR_NOMEM = 3
+
+    class FmmdsError(RuntimeError):
+        def __init__(self, status, msg=""):
+            super().__init__(msg)
+            self.status = status
+
+    @staticmethod
+    def batch_footprint(off, lev):
+        return int(off[-1]) * 10
+
+
+SIZES = (100, 200, 300, 400, 500, 600, 700, 800)
+
+
+def _server(budget, slots=4):
+    srv = S.Server.__new__(S.Server)
+    srv.torch, srv.F = _Torch, _Lib
+    srv.x0 = [np.zeros((n, 3), np.float32) for n in SIZES]
+    srv.levels = [3] * len(SIZES)
+    srv.n = list(SIZES)
+    srv.sigma, srv.seed = 1e-3, 8
+    srv.max_batch_points, srv.max_batch_sets = 1 << 24, 64
+    srv.slots = [S._Slot(stream=None) for _ in range(slots)]
+    srv.budget, srv.keep_inputs, srv.stall_seconds = budget, set(), 5.0
+    srv._displace = lambda s, stream: srv.step.__setitem__(s, srv.step[s] + 1)
+    srv.reset()
+    return srv
+
+
+@pytest.mark.parametrize("budget", [10 ** 6, 30000, 9000, 8000])
+def test_all_requests_served_within_budget(budget):
+    arr = np.linspace(0, 0.005, 300)
+    pick = np.random.default_rng(1).integers(0, len(SIZES), 300)
+    srv = _server(budget)
+    peak = []
+    reqs = srv.run(arr, pick, on_complete=lambda s, r: peak.append(s.resident))
+    assert all(r.done >= r.arrival >= 0 for r in reqs)
+    assert max(peak) <= budget
+    # each system's steps were taken in arrival order
+    per = {}
+    for r in reqs:
+        per.setdefault(r.system, []).append(r.step)
+    for steps in per.values():
+        assert steps == sorted(steps) and len(set(steps)) == len(steps)
+    if budget >= sum(SIZES) * 10 * 2:
+        assert srv.evictions == 0
+    srv.close()
+
+
+def test_batches_hold_several_requests():
+    arr = np.zeros(64)
+    pick = np.arange(64) % len(SIZES)
+    srv = _server(10 ** 7, slots=1)
+    reqs = srv.run(arr, pick)
+    by_launch = {}
+    for r in reqs:
+        by_launch.setdefault(r.launched, []).append(r.system)
+    assert max(len(v) for v in by_launch.values()) == len(SIZES)  # one per system per batch
+    srv.close()
+
+
+def test_oversize_request_rejected():
+    srv = _server(7999)
+    with pytest.raises(_Lib.FmmdsError) as e:
+        srv.run(np.zeros(3), np.asarray([7, 0, 1]))
+    assert e.value.status == _Lib.ERR_NOMEM
