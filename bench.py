@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (scales HBM counters)")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event timing (no roofline object)")
     args = ap.parse_args()
@@ -186,6 +188,13 @@ def main():
     if not os.path.exists(F.LIB_PATH):
         from paper_1301_1704_amd import _compile as hb
         hb.build()
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     c = workload(args.workload)
     log(f"workload {c['name']}: generating inputs")
     src = torch.from_numpy(c["src"]).cuda()

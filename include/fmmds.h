@@ -197,6 +197,11 @@ void fmmds_batch_free(fmmds_batch* b);
  * synchronizes every device the cache holds memory of and returns all cached
  * blocks to HIP. Memory of live trees is not affected. */
 void fmmds_trim(void);
+/* Counters of that cache (host pointers, each may be NULL): allocations
+ * served from it, allocations that went to HIP and their bytes, and the bytes
+ * it currently holds unused. */
+void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,
+                      uint64_t* cached_bytes);
 
 /*
  * Diagnostics: per-kernel timing. While enabled, every kernel a build

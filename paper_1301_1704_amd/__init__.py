@@ -81,6 +81,8 @@ def _lib():
         L.fmmds_free.argtypes = [C.POINTER(TreeStruct)]
         L.fmmds_free.restype = None
         L.fmmds_trim.restype = None
+        L.fmmds_cache_info.argtypes = [C.POINTER(_u64)] * 4
+        L.fmmds_cache_info.restype = None
         L.fmmds_batch_create.argtypes = [_vp, _vp, _u32, C.POINTER(Options), C.POINTER(_vp)]
         L.fmmds_batch_create.restype = C.c_int
         L.fmmds_batch_launch.argtypes = [_vp, _vp, C.c_int]
@@ -115,7 +117,7 @@ def _lib():
 
 def exported_symbols():
     return ["fmmds_build", "fmmds_neighbors", "fmmds_interactions", "fmmds_free",
-            "fmmds_trim", "fmmds_profile_enable", "fmmds_profile_reset",
+            "fmmds_trim", "fmmds_cache_info", "fmmds_profile_enable", "fmmds_profile_reset",
             "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
@@ -132,6 +134,14 @@ def batch_footprint(set_offsets, levels) -> int:
     if st != OK:
         raise FmmdsError(st, "fmmds_batch_footprint")
     return int(out.value)
+
+
+def cache_info() -> dict:
+    """Counters of the library's device-memory cache."""
+    v = [_u64() for _ in range(4)]
+    _lib().fmmds_cache_info(*[C.byref(x) for x in v])
+    return {"hits": v[0].value, "misses": v[1].value, "miss_bytes": v[2].value,
+            "cached_bytes": v[3].value}
 
 
 def trim():

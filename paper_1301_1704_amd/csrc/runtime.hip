@@ -41,7 +41,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // and over (rebuilds of moving particles, benchmark loops), and a round trip
 // through the HIP allocator costs tens to hundreds of microseconds. Released
 // blocks stay cached per device and are handed out again for a request of at
-// most the block's size and at least 7/8 of it. A block released on stream S
+// least half the block's size. A block released on stream S
 // may still be used by work queued on S: it is reused at once on S (stream
 // order protects it); another stream first waits on an event recorded on S at
 // release time. fmmds_trim returns every cached block to HIP.
@@ -74,12 +74,17 @@ struct CachedBlock {
   EventRef ready;  // completes when the releasing stream is done with the block
 };
 std::mutex g_cache_mu;
+uint64_t g_cache_hits = 0, g_cache_misses = 0, g_cache_miss_bytes = 0;
 std::map<int, std::multimap<size_t, CachedBlock>> g_cache;  // device -> size -> block
 std::map<void*, size_t> g_live;                              // pointer -> bytes
 
+// Size classes: 4 KiB steps up to 1 MiB, then 8 classes per power of two
+// (at most 12.5% over the request), so that blocks released by one build
+// fit the next build of a similar but not identical shape.
 size_t cache_round(size_t bytes) {
   if (bytes <= (1u << 20)) return round_up(bytes, 4096);
-  return round_up(bytes, 2u << 20);
+  const int k = 63 - __builtin_clzll((unsigned long long)bytes);
+  return round_up(bytes, (size_t)1 << (k - 3));
 }
 
 void* cache_alloc(size_t bytes, hipStream_t stream) {
@@ -90,8 +95,8 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
     std::lock_guard<std::mutex> g(g_cache_mu);
     auto& m = g_cache[dev];
     auto best = m.end();
-    for (auto it = m.lower_bound(bytes); it != m.end() && it->first - bytes <= it->first / 8;
-         ++it) {
+    // any cached block of the same class or up to twice the size
+    for (auto it = m.lower_bound(bytes); it != m.end() && it->first <= 2 * bytes; ++it) {
       if (it->second.stream == stream) {
         best = it;
         break;
@@ -104,8 +109,11 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
       if (b.stream != stream && b.ready && b.ready->ev)
         ck(hipStreamWaitEvent(stream, b.ready->ev, 0));
       g_live[b.p] = b.bytes;
+      ++g_cache_hits;
       return b.p;
     }
+    ++g_cache_misses;
+    g_cache_miss_bytes += bytes;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -1297,6 +1305,18 @@ uint32_t fmmds_batch_sort_items(const fmmds_batch* b) {
 }
 
 void fmmds_batch_free(fmmds_batch* b) { fmmds::batch_free((fmmds::BatchImpl*)b); }
+
+void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,
+                      uint64_t* cached_bytes) {
+  std::lock_guard<std::mutex> g(fmmds::g_cache_mu);
+  uint64_t c = 0;
+  for (auto& d : fmmds::g_cache)
+    for (auto& kv : d.second) c += kv.first;
+  if (hits) *hits = fmmds::g_cache_hits;
+  if (misses) *misses = fmmds::g_cache_misses;
+  if (miss_bytes) *miss_bytes = fmmds::g_cache_miss_bytes;
+  if (cached_bytes) *cached_bytes = c;
+}
 
 void fmmds_trim(void) {
   std::lock_guard<std::mutex> g(fmmds::g_cache_mu);

@@ -85,7 +85,26 @@ class Server:
         self.budget = hbm_budget
         self.keep_inputs = set(keep_inputs)  # request ids whose inputs are kept (tests)
         self.stall_seconds = stall_seconds
+        self._prewarm()
         self.reset()
+
+    def _prewarm(self):
+        """One-time initialization (random-number kernels on every stream, the
+        batched path) before any request is timed."""
+        torch, F = self.torch, self.F
+        pts = np.ascontiguousarray(I.uniform_points(1, 300))
+        for slot in self.slots:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1)
+            with torch.cuda.stream(slot.stream):
+                torch.randn((16, 3), generator=g, device="cuda")
+                x = torch.from_numpy(pts).cuda()
+            b = F.Batch(np.asarray([0, 100, 300], np.uint64), np.asarray([2, 3], np.uint8),
+                        stream=slot.stream)
+            b.launch(x)
+            b.wait()
+            b.free()
+        torch.cuda.synchronize()
 
     # ------------------------------------------------------------- state
     def reset(self):
@@ -100,6 +119,7 @@ class Server:
         self.kept_inputs = {}
         self.results = {}                       # rid -> (live id, set index) while resident
         self.evictions = 0
+        self.host_ms = {"create": [], "stage": [], "launch": [], "wait": [], "release": []}
         torch.cuda.synchronize()
 
     def _displace(self, s: int, stream):
@@ -141,7 +161,10 @@ class Server:
         off = np.zeros(len(reqs) + 1, dtype=np.uint64)
         off[1:] = np.cumsum(sizes)
         lev = np.asarray([self.levels[r.system] for r in reqs], dtype=np.uint8)
+        tc = time.perf_counter()
         b = F.Batch(off, lev, stream=slot.stream)
+        self.host_ms["create"].append((time.perf_counter() - tc) * 1e3)
+        tc = time.perf_counter()
         with torch.cuda.stream(slot.stream):
             slot.xbuf = torch.empty((int(off[-1]), 3), dtype=torch.float32, device="cuda")
         for i, r in enumerate(reqs):
@@ -152,7 +175,10 @@ class Server:
                 if r.rid in self.keep_inputs:
                     self.kept_inputs[r.rid] = self.x[r.system].clone()
             r.launched = now
+        self.host_ms["stage"].append((time.perf_counter() - tc) * 1e3)
+        tc = time.perf_counter()
         b.launch(slot.xbuf)
+        self.host_ms["launch"].append((time.perf_counter() - tc) * 1e3)
         ev = torch.cuda.Event()
         ev.record(slot.stream)
         slot.batch, slot.event, slot.reqs = b, ev, reqs
@@ -163,7 +189,9 @@ class Server:
         slot.lid = lid
 
     def _finish(self, slot: _Slot, t0: float):
+        tc = time.perf_counter()
         slot.batch.wait()
+        self.host_ms["wait"].append((time.perf_counter() - tc) * 1e3)
         done = time.perf_counter() - t0
         lid = slot.lid
         for i, r in enumerate(slot.reqs):
@@ -172,7 +200,9 @@ class Server:
             self.latest[r.system] = (lid, i)
             self.results[r.rid] = (lid, i)
             if old is not None:
+                tc = time.perf_counter()
                 self._release(old[0])
+                self.host_ms["release"].append((time.perf_counter() - tc) * 1e3)
         slot.batch, slot.event, slot.reqs, slot.xbuf = None, None, [], None
 
     def tree_of(self, rid: int):
@@ -282,6 +312,10 @@ def run_sequential(systems, levels, arrivals, picks, *, sigma=1e-3, seed=8):
     step = [0] * len(x)
     latest = [None] * len(x)
     reqs = [Request(i, int(s), float(a)) for i, (a, s) in enumerate(zip(arrivals, picks))]
+    g = torch.Generator(device="cuda")  # one-time initialization, untimed
+    g.manual_seed(1)
+    torch.randn((16, 3), generator=g, device="cuda")
+    F.build(torch.from_numpy(I.uniform_points(1, 300)).cuda(), None, max_level=3).free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in reqs:
@@ -310,6 +344,10 @@ def latency_stats(reqs, skip: int = 0) -> dict:
     rs = reqs[skip:]
     lat = np.asarray([r.done - r.arrival for r in rs]) * 1e3
     span = max(r.done for r in rs) - min(r.arrival for r in rs)
+    wait = np.asarray([r.launched - r.arrival for r in rs]) * 1e3
+    serve = np.asarray([r.done - r.launched for r in rs]) * 1e3
     return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "builds_per_s": len(rs) / span if span > 0 else float("nan")}
+            "builds_per_s": len(rs) / span if span > 0 else float("nan"),
+            "p99_queue_ms": float(np.percentile(wait, 99)),
+            "p99_service_ms": float(np.percentile(serve, 99))}
