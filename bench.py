@@ -11,6 +11,7 @@ stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -39,6 +40,112 @@ def workload(name: str):
     if name == "small":
         return I.config_plain_small()
     raise SystemExit(f"unknown workload {name}")
+
+
+TRAFFIC_FILES = {"uniform": "hbm_traffic_uniform_2x2p24_L8.md",
+                 "nonuniform": "hbm_traffic_nonuniform_2x2p24_L10_s64.md"}
+
+
+def counter_traffic(workload_name: str, kernel_class: str):
+    """HBM bytes per launch of one kernel class from the committed counter
+    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, already scaled by a copy of
+    known size), or None when there is none or the kernel's source file has
+    changed since the counters were taken."""
+    name = TRAFFIC_FILES.get(workload_name)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    for ln in open(path):
+        parts = ln.split()
+        if len(parts) < 2 or parts[0] != "traffic" or parts[1] != kernel_class:
+            continue
+        kv = dict(p.split("=", 1) for p in parts[2:])
+        src = os.path.join(ROOT, kv["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha"]:
+            return None
+        return {"read": float(kv["read_bytes_avg"]), "write": float(kv["write_bytes_avg"]),
+                "source": name}
+    return None
+
+
+KERNEL_CLASS = [  # rocprofv3 kernel name (namespace and arguments stripped) -> class
+    ("k_lists<unsigned long, unsigned int, 1>", "list_fill"),
+    ("k_lists<unsigned int, unsigned int, 1>", "list_fill"),
+    ("k_lists<unsigned long, unsigned int, 0>", "list_count"),
+    ("k_lists<unsigned int, unsigned int, 0>", "list_count"),
+    ("k_scan_counts2", "scan_counts"), ("k_sort_pass", "sort_pass"), ("k_keygen", "keygen"),
+    ("k_digit_offsets", "digit_offsets"), ("k_zero", "zero"), ("k_leaf", "leaf"),
+    ("k_level", "level"), ("k_max_occupancy", "max_occupancy")]
+KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_counts": "lists.hip",
+                 "sort_pass": "sort.hip", "keygen": "sort.hip", "digit_offsets": "sort.hip",
+                 "zero": "sort.hip", "leaf": "tables.hip", "level": "tables.hip",
+                 "max_occupancy": "tables.hip"}
+COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-profile "
+                "--copy-calibration")
+
+
+def _kernel_class(name: str):
+    base = name.split("(")[0].replace("void ", "").replace("fmmds::", "").strip()
+    for pat, cls in KERNEL_CLASS:
+        if base == pat or base.split("<")[0] == pat:
+            return cls
+    return None
+
+
+def counter_summary(fetch_csv: str, write_csv: str, out: str, workload_name: str):
+    """Writes the per-kernel HBM traffic summary (profiles/) from two rocprofv3
+    --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+    each scaled by what the counter reads for the 1 GiB copy that
+    --copy-calibration runs first."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, counter):
+        per, copy = defaultdict(list), []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"):
+                copy.append(v)
+            cls = _kernel_class(r["Kernel_Name"])
+            if cls:
+                per[cls].append(v)
+        return per, max(copy)
+
+    f, fcopy = load(fetch_csv, "FETCH_SIZE")
+    w, wcopy = load(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fs, ws = gib_kib / fcopy, gib_kib / wcopy
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} --output-format csv -d <dir> -o run"
+           " -- python3 <repo>/bench.py --workload " + workload_name + " " + COUNTER_ARGS)
+    lines = [f"# HBM traffic per dispatch, workload `{workload_name}` (rocprofv3 FETCH_SIZE / WRITE_SIZE)",
+             "", "Counters were collected in two runs of their own:", "", "```",
+             cmd.format(c="FETCH_SIZE"), cmd.format(c="WRITE_SIZE"),
+             f"python3 bench.py --counter-summary <fetch dir>/run_counter_collection.csv "
+             f"<write dir>/run_counter_collection.csv {os.path.relpath(out, ROOT)} "
+             f"--workload {workload_name}", "```", "",
+             f"Calibration: the 1 GiB device-to-device copy run first reads as FETCH_SIZE "
+             f"{fcopy:.0f} KiB and WRITE_SIZE {wcopy:.0f} KiB, so reads are scaled by {fs:.3f} "
+             f"and writes by {ws:.3f}.", "",
+             "| kernel class | dispatches | read MB / dispatch | write MB / dispatch | source |",
+             "|---|---:|---:|---:|---|"]
+    data = []
+    for cls in sorted(f):
+        fv = [x * fs * 1024 for x in f[cls]]
+        wv = [x * ws * 1024 for x in w.get(cls, [0.0])]
+        src = "paper_1301_1704_amd/csrc/" + KERNEL_SOURCE[cls]
+        sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        rb, wb = sum(fv) / len(fv), sum(wv) / len(wv)
+        lines.append(f"| {cls} | {len(fv)} | {rb / 1e6:.1f} | {wb / 1e6:.1f} | {src} |")
+        data.append(f"traffic {cls} read_bytes_avg={rb:.0f} write_bytes_avg={wb:.0f} "
+                    f"dispatches={len(fv)} source={src} sha={sha}")
+    lines += ["", "Averages over every dispatch of the runs (all builds have the same shape). "
+              "Lines read by bench.py (`sha` = the kernel source the counters were taken "
+              "with; bench.py reports no traffic once it differs):", "", "```"] + data + ["```"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(name: str):
@@ -176,7 +283,12 @@ def main():
                     help="run a 1 GiB device-to-device copy first (scales HBM counters)")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event timing (no roofline object)")
+    ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
+                    help="write the HBM traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.counter_summary:
+        counter_summary(*args.counter_summary, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent point sets shard trivially, one set spans one GPU)", file=sys.stderr)
@@ -260,11 +372,18 @@ def main():
         avg_ms = v["total_ms"] / v["launches"]
         achieved = per_launch / (avg_ms * 1e6)
         total = sum(b["total_ms"] for b in breakdown.values())
+        tr = counter_traffic(args.workload, dominant)
         line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": None if tr is None else tr["read"] + tr["write"],
                             "kernel": dominant, "launches": v["launches"],
                             "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch,
                             "kernel_time_share": breakdown[dominant]["total_ms"] / total}
+        if tr is not None:
+            line["roofline"]["traffic_detail"] = {
+                "read_bytes": tr["read"], "write_bytes": tr["write"],
+                "over_algorithmic": (tr["read"] + tr["write"]) / per_launch,
+                "counters": "profiles/" + tr["source"]}
         line["kernels"] = {k: {"launches": b["launches"],
                                "avg_us": round(1e3 * b["total_ms"] / b["launches"], 2),
                                "GBps": round(b["bytes"] / (b["total_ms"] * 1e6), 1)}

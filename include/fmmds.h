@@ -67,7 +67,7 @@ typedef enum fmmds_status {
 } fmmds_status;
 
 /* Optional allocator: return `bytes` of device memory usable on `stream`
- * (a hipStream_t), or NULL on failure. `release` gets back exactly the
+ * (a hipStream_t), aligned to 256 bytes, or NULL on failure. `release` gets back exactly the
  * pointers `alloc` returned, with the same byte counts. */
 typedef void* (*fmmds_alloc_fn)(void* ctx, size_t bytes, void* stream);
 typedef void (*fmmds_release_fn)(void* ctx, void* ptr, size_t bytes, void* stream);
@@ -191,6 +191,37 @@ uint64_t fmmds_batch_bytes(const fmmds_batch* b);
 /* Sort tile size (elements per thread: 8, 12 or 16) the batch uses. */
 uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
 void fmmds_batch_free(fmmds_batch* b);
+
+/*
+ * Serving support: one time step of moving particle systems, for the
+ * dynamic problems the paper motivates (Section 1, Section 2.5), so that a
+ * rebuild request runs on the GPU from the step to the lists. Not a step of
+ * the paper's build.
+ *
+ * Every coordinate of every listed system moves by sigma * z, z ~ N(0, 1),
+ * and is clamped into [0, 1 - 2^-24] (NaN is left as it is). z is counter
+ * based: coordinate d of point i uses output c = 3i + d of the splitmix64
+ * stream `seed` (output c = mix(seed + (c + 1) * 0x9E3779B97F4A7C15) with
+ * the published mixing constants); u1 = ((h >> 40) + 1) * 2^-24,
+ * u2 = ((h >> 16) & 0xFFFFFF) * 2^-24, z = sqrt(-2 ln u1) cos(2 pi u2) in
+ * FP32. A system's result therefore does not depend on which other systems
+ * share the call.
+ *   sets:   host array of n_sets entries; xyz is device memory of n points
+ *           (AoS FP32), updated in place; distinct entries must not overlap.
+ *   out:    device or NULL; when set, the displaced points of entry k are
+ *           also written at points out_first .. out_first + n - 1 of `out`
+ *           (so a batch input can be assembled in the same pass).
+ *   stream: hipStream_t the work is ordered on (NULL = null stream).
+ * Returns at once (asynchronous); FMMDS_ERR_ARG for NULL pointers or n = 0.
+ */
+typedef struct fmmds_displace_set {
+  float* xyz;
+  uint64_t n;
+  uint64_t seed;
+  uint64_t out_first;
+} fmmds_displace_set;
+fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, float sigma,
+                            float* out, void* stream);
 
 /* Memory the library allocates itself (opt->alloc == NULL) is cached after
  * release, per device, and reused by later builds of similar size. This call

@@ -99,6 +99,8 @@ def _lib():
         L.fmmds_batch_sort_items.restype = _u32
         L.fmmds_batch_free.argtypes = [_vp]
         L.fmmds_batch_free.restype = None
+        L.fmmds_displace.argtypes = [C.POINTER(DisplaceSet), _u32, C.c_float, _vp, _vp]
+        L.fmmds_displace.restype = C.c_int
         L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
         L.fmmds_profile_enable.restype = None
         L.fmmds_profile_reset.restype = None
@@ -121,7 +123,30 @@ def exported_symbols():
             "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
-            "fmmds_batch_free"]
+            "fmmds_batch_free", "fmmds_displace"]
+
+
+class DisplaceSet(C.Structure):
+    _fields_ = [("xyz", _vp), ("n", _u64), ("seed", _u64), ("out_first", _u64)]
+
+
+def displace(items, sigma: float, out=None, stream=None):
+    """One time step of moving systems on the GPU (fmmds_displace): `items` is
+    a list of (xyz tensor (n, 3) float32 CUDA, seed, out_first); each tensor is
+    updated in place and, when `out` is given, also copied to rows
+    out_first.. of `out`. Ordered on `stream` (default: the current stream)."""
+    import torch
+    arr = (DisplaceSet * len(items))()
+    for k, (x, seed, first) in enumerate(items):
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("xyz must be a contiguous float32 CUDA tensor")
+        arr[k].xyz, arr[k].n = x.data_ptr(), x.shape[0]
+        arr[k].seed, arr[k].out_first = int(seed) & 0xFFFFFFFFFFFFFFFF, int(first)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = _lib().fmmds_displace(arr, len(items), float(sigma),
+                               None if out is None else out.data_ptr(), s.cuda_stream)
+    if st != OK:
+        raise FmmdsError(st, "fmmds_displace")
 
 
 def batch_footprint(set_offsets, levels) -> int:

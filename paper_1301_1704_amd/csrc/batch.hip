@@ -121,18 +121,26 @@ void launch_batch_first(const LevelPtrs& lp, uint32_t L_all, const uint32_t* n_b
                      set_off, n_sets, first);
 }
 
-// Set-local tables of level l in the per-set layout: keys, parents and box
-// rows at their batch rank g; bookmarks and first children at g + set, which
-// leaves one slot after each set for its sentinel.
-__global__ __launch_bounds__(256) void k_batch_rebase(
-    uint32_t l, const uint32_t* __restrict__ n_l, const uint64_t* __restrict__ gkey,
-    const uint32_t* __restrict__ gbegin, const uint32_t* __restrict__ gparent,
-    const uint32_t* __restrict__ gchild, const uint32_t* __restrict__ first_prev,
-    const uint32_t* __restrict__ first_cur, const uint32_t* __restrict__ first_next,
-    const uint64_t* __restrict__ set_off, uint64_t* __restrict__ fkey,
-    uint32_t* __restrict__ fbegin, uint32_t* __restrict__ fparent,
-    uint32_t* __restrict__ fchild) {
-  const uint32_t n = *n_l;
+// Set-local tables in the per-set layout, every level in one launch
+// (blockIdx.y = level): keys, parents and box rows at their batch rank g;
+// bookmarks and first children at g + set, which leaves one slot after each
+// set for its sentinel.
+__global__ __launch_bounds__(256) void k_batch_rebase(RebaseArgs a) {
+  const uint32_t l = blockIdx.y;
+  const uint32_t n = *a.n_l[l];
+  const uint64_t per = (uint64_t)a.n_sets + 1;
+  const uint32_t* first_cur = a.first + l * per;
+  const uint32_t* first_prev = l >= 1 ? a.first + (l - 1) * per : nullptr;
+  const uint32_t* first_next = l < a.L ? a.first + (l + 1) * per : nullptr;
+  const uint64_t* gkey = a.gkey[l];
+  const uint32_t* gbegin = a.gbegin[l];
+  const uint32_t* gparent = a.gparent[l];
+  const uint32_t* gchild = a.gchild[l];
+  uint64_t* fkey = a.fkey[l];
+  uint32_t* fbegin = a.fbegin[l];
+  uint32_t* fparent = a.fparent[l];
+  uint32_t* fchild = a.fchild[l];
+  const uint64_t* set_off = a.set_off;
   for (uint64_t g = blockIdx.x * 256ull + threadIdx.x; g < n; g += gridDim.x * 256ull) {
     const uint64_t key = gkey[g];
     const uint32_t set = (uint32_t)(key >> (3 * l));
@@ -147,27 +155,27 @@ __global__ __launch_bounds__(256) void k_batch_rebase(
   }
 }
 
-void launch_batch_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
-                         const uint32_t* gbegin, const uint32_t* gparent, const uint32_t* gchild,
-                         const uint32_t* first_prev, const uint32_t* first_cur,
-                         const uint32_t* first_next, const uint64_t* set_off, uint64_t* fkey,
-                         uint32_t* fbegin, uint32_t* fparent, uint32_t* fchild, hipStream_t s) {
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 4096));
-  hipLaunchKernelGGL(k_batch_rebase, dim3(grid), dim3(256), 0, s, l, n_l, gkey, gbegin, gparent,
-                     gchild, first_prev, first_cur, first_next, set_off, fkey, fbegin, fparent,
-                     fchild);
+void launch_batch_rebase(const RebaseArgs& a, uint32_t max_cap, hipStream_t s) {
+  const uint32_t gx = std::max<uint32_t>(1, std::min<uint32_t>(div_up(max_cap, 256), 2048));
+  hipLaunchKernelGGL(k_batch_rebase, dim3(gx, a.L + 1), dim3(256), 0, s, a);
 }
 
-// List offsets of level l relative to each set's first receiver, in the
-// per-set layout (slot g + set, sentinel after each set), and each set's base
-// into the batch's entry arrays (base[n_sets] = the level's total).
-__global__ __launch_bounds__(256) void k_batch_list_rebase(
-    uint32_t l, const uint32_t* __restrict__ n_l, const uint64_t* __restrict__ gkey,
-    const uint32_t* __restrict__ first_cur, const uint32_t* __restrict__ goff2,
-    const uint32_t* __restrict__ goff4, uint32_t* __restrict__ loff2,
-    uint32_t* __restrict__ loff4, uint32_t* __restrict__ base2, uint32_t* __restrict__ base4,
-    uint32_t n_sets) {
-  const uint32_t n = *n_l;
+// List offsets relative to each set's first receiver, in the per-set layout
+// (slot g + set, sentinel after each set), and each set's base into the
+// batch's entry arrays (base[n_sets] = the level's total); levels 2..L in one
+// launch (blockIdx.y = level - 2).
+__global__ __launch_bounds__(256) void k_batch_list_rebase(ListRebaseArgs a) {
+  const uint32_t l = blockIdx.y + 2;
+  const uint32_t n = *a.n_l[l];
+  const uint64_t per = (uint64_t)a.n_sets + 1;
+  const uint32_t* first_cur = a.first + l * per;
+  const uint64_t* gkey = a.gkey[l];
+  const uint32_t* goff2 = a.goff2[l];
+  const uint32_t* goff4 = a.goff4[l];
+  uint32_t* loff2 = a.loff2[l];
+  uint32_t* loff4 = a.loff4[l];
+  uint32_t* base2 = a.base + (2 * l) * per;
+  uint32_t* base4 = a.base + (2 * l + 1) * per;
   for (uint64_t g = blockIdx.x * 256ull + threadIdx.x; g < n; g += gridDim.x * 256ull) {
     const uint32_t set = (uint32_t)(gkey[g] >> (3 * l));
     const uint32_t f = first_cur[set];
@@ -183,19 +191,16 @@ __global__ __launch_bounds__(256) void k_batch_list_rebase(
       loff4[g + 1 + set] = goff4[g + 1] - b4;
     }
     if (g + 1 == n) {
-      base2[n_sets] = goff2[n];
-      base4[n_sets] = goff4[n];
+      base2[a.n_sets] = goff2[n];
+      base4[a.n_sets] = goff4[n];
     }
   }
 }
 
-void launch_batch_list_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
-                              const uint32_t* first_cur, const uint32_t* goff2,
-                              const uint32_t* goff4, uint32_t* loff2, uint32_t* loff4,
-                              uint32_t* base2, uint32_t* base4, uint32_t n_sets, hipStream_t s) {
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 4096));
-  hipLaunchKernelGGL(k_batch_list_rebase, dim3(grid), dim3(256), 0, s, l, n_l, gkey, first_cur,
-                     goff2, goff4, loff2, loff4, base2, base4, n_sets);
+void launch_batch_list_rebase(const ListRebaseArgs& a, uint32_t max_cap, hipStream_t s) {
+  if (a.L < 2) return;
+  const uint32_t gx = std::max<uint32_t>(1, std::min<uint32_t>(div_up(max_cap, 256), 2048));
+  hipLaunchKernelGGL(k_batch_list_rebase, dim3(gx, a.L - 1), dim3(256), 0, s, a);
 }
 
 }  // namespace fmmds

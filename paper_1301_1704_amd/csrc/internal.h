@@ -86,9 +86,11 @@ void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint3
                        hipStream_t s);
 void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
                       const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s);
-void launch_scan_counts(const uint32_t* cnt, uint32_t n, uint32_t* off, uint64_t* total,
-                        uint32_t* overflow, uint64_t* status, uint32_t* tile_counter,
-                        hipStream_t s, const uint32_t* n_dev = nullptr);
+uint32_t scan_tiles(uint32_t n);
+void launch_scan_counts2(const uint32_t* cnt2, const uint32_t* cnt4, uint32_t n, uint32_t* off2,
+                         uint32_t* off4, uint64_t* total2, uint64_t* total4, uint32_t* overflow,
+                         uint64_t* status2, uint64_t* status4, uint32_t* tile_counter,
+                         hipStream_t s, const uint32_t* n_dev = nullptr);
 
 // ---- batch.hip kernels
 struct LevelPtrs {
@@ -100,14 +102,43 @@ void launch_batch_keygen(const float* xyz, uint32_t n, const uint64_t* set_off, 
                          hipStream_t s);
 void launch_batch_first(const LevelPtrs& lp, uint32_t L_all, const uint32_t* n_boxes,
                         const uint64_t* set_off, uint32_t n_sets, uint32_t* first, hipStream_t s);
-void launch_batch_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
-                         const uint32_t* gbegin, const uint32_t* gparent, const uint32_t* gchild,
-                         const uint32_t* first_prev, const uint32_t* first_cur,
-                         const uint32_t* first_next, const uint64_t* set_off, uint64_t* fkey,
-                         uint32_t* fbegin, uint32_t* fparent, uint32_t* fchild, hipStream_t s);
-void launch_batch_list_rebase(uint32_t l, uint32_t cap, const uint32_t* n_l, const uint64_t* gkey,
-                              const uint32_t* first_cur, const uint32_t* goff2,
-                              const uint32_t* goff4, uint32_t* loff2, uint32_t* loff4,
-                              uint32_t* base2, uint32_t* base4, uint32_t n_sets, hipStream_t s);
+struct RebaseArgs {  // every level 0..L of a batch
+  const uint32_t* n_l[kMaxLevel + 1];
+  const uint64_t* gkey[kMaxLevel + 1];
+  const uint32_t* gbegin[kMaxLevel + 1];
+  const uint32_t* gparent[kMaxLevel + 1];  // nullptr at level 0
+  const uint32_t* gchild[kMaxLevel + 1];   // nullptr at level L
+  uint64_t* fkey[kMaxLevel + 1];
+  uint32_t* fbegin[kMaxLevel + 1];
+  uint32_t* fparent[kMaxLevel + 1];
+  uint32_t* fchild[kMaxLevel + 1];
+  const uint32_t* first;  // first[l * (n_sets + 1) + i]
+  const uint64_t* set_off;
+  uint32_t n_sets, L;
+};
+void launch_batch_rebase(const RebaseArgs& a, uint32_t max_cap, hipStream_t s);
+struct ListRebaseArgs {  // levels 2..L of a batch
+  const uint32_t* n_l[kMaxLevel + 1];
+  const uint64_t* gkey[kMaxLevel + 1];
+  const uint32_t* goff2[kMaxLevel + 1];
+  const uint32_t* goff4[kMaxLevel + 1];
+  uint32_t* loff2[kMaxLevel + 1];
+  uint32_t* loff4[kMaxLevel + 1];
+  const uint32_t* first;
+  uint32_t* base;  // base[(2l + k) * (n_sets + 1) + i], k = 0 (E2) or 1 (E4)
+  uint32_t n_sets, L;
+};
+void launch_batch_list_rebase(const ListRebaseArgs& a, uint32_t max_cap, hipStream_t s);
+
+// ---- displace.hip
+constexpr uint32_t kDisplaceSets = 32;  // systems per launch (kernel-argument struct)
+struct DisplaceArgs {
+  float* xyz[kDisplaceSets];
+  uint64_t seed[kDisplaceSets];
+  uint64_t first[kDisplaceSets + 1];  // prefix of point counts; first[n] = total
+  uint64_t out_first[kDisplaceSets];
+  uint32_t n;
+};
+void launch_displace(const DisplaceArgs& a, float sigma, float* out, hipStream_t s);
 
 }  // namespace fmmds

@@ -23,16 +23,22 @@
 
 namespace fmmds {
 
-// Work mapping: one half-wave (32 lanes) per receiver box p of level l - 1;
-// lane j takes the j-th entry s of E2(p) (at most 27). The lane computes,
-// once for all receiver children of p, the offset of s from p, s's child mask
-// and first child rank, and for each of the 8 child octants q the number of
-// s's children adjacent to a receiver child in octant q. Two packed
-// half-wave scans then give every lane its place in the E2 and E4 list of
-// every receiver child of p at once (E4 places follow from the scan of all
-// children minus the E2 places). For each receiver child r of p, in octant
-// order, the lanes put their entries into a per-half-wave LDS buffer and the
-// half-wave copies r's two lists out contiguously, 128 bytes per store.
+// Counting: one half-wave (32 lanes) per receiver box p of level l - 1; lane
+// j takes the j-th entry s of E2(p) (at most 27). The lane computes the
+// offset of s from p, s's child mask and, for each of the 8 child octants q,
+// the number of s's children adjacent to a receiver child in octant q; two
+// packed half-wave scans give the E2 count of every receiver child of p at
+// once (E4 = all children minus E2).
+//
+// Filling: two receiver boxes p per wave, one per half-wave for the setup.
+// The children of all s in E2(p), in ascending rank, form one union list U
+// (at most 216 boxes), the same for every receiver child of p; the half-wave
+// writes U once to LDS together with, per entry, the 8-bit mask of receiver
+// octants it is adjacent to. Then the whole wave takes each p in turn: each
+// lane keeps its share of U in registers, and for each receiver child the
+// wave splits U into the child's E2 and E4 lists with one ballot per 64
+// entries: order is kept, so both come out ascending, and each chunk is
+// stored to two contiguous ranges.
 //
 // Offsets per axis come from dilated-integer subtraction on the Morton keys:
 // with only one axis' bits kept in both operands, borrows run through the
@@ -40,8 +46,7 @@ namespace fmmds {
 // difference of the two coordinates on that axis. Here it is 0, +1 or -1,
 // i.e. 0, the axis' lowest bit, or all of the axis' bits.
 constexpr uint64_t kAxisX = 0x1249249249249249ull;
-constexpr int kHalfBuf = 224;  // E4 at [0, 189), E2 at [kE2At, kE2At + 27)
-constexpr int kE2At = 192;
+constexpr int kUnion = 256;  // >= 27 * 8 children of E2(p)
 
 template <typename A>
 __device__ __forceinline__ int axis_delta(A sk, A pk, A axis_mask, A axis_low) {
@@ -67,12 +72,9 @@ __device__ __forceinline__ uint32_t octant_field(uint32_t a, uint32_t b, uint32_
   return q < 4 ? (a >> (8 + 6 * q)) & 63u : (b >> (6 * (q - 4))) & 63u;
 }
 
-template <typename KeyT, typename A, int MODE>  // MODE 0: count, 1: fill
-__global__ __launch_bounds__(256) void k_lists(
-    ListLevelArgs a, uint32_t* __restrict__ cnt2, uint32_t* __restrict__ cnt4,
-    const uint32_t* __restrict__ off2, const uint32_t* __restrict__ off4,
-    uint32_t* __restrict__ ent2, uint32_t* __restrict__ ent4) {
-  __shared__ uint32_t s_buf[MODE == 1 ? 8 : 1][kHalfBuf];
+template <typename KeyT, typename A>
+__global__ __launch_bounds__(256) void k_list_count(ListLevelArgs a, uint32_t* __restrict__ cnt2,
+                                                    uint32_t* __restrict__ cnt4) {
   const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
   const uint32_t j = threadIdx.x & 31u, h = threadIdx.x >> 5;
@@ -80,8 +82,8 @@ __global__ __launch_bounds__(256) void k_lists(
   const uint32_t n_up = a.n_recv_up_dev ? *a.n_recv_up_dev : a.n_recv_up;
   if (p >= n_up) return;  // whole half-wave
   // upbase: batch rank of the set's first box at level - 1 (parent-level E2
-  // entries are stored relative to it); base: the same at level l.
-  uint32_t j0, cnt, upbase = 0, base = 0;
+  // entries are stored relative to it).
+  uint32_t j0, cnt, upbase = 0;
   if (a.up_all) {
     j0 = 0;
     cnt = a.n_src_up;
@@ -91,15 +93,13 @@ __global__ __launch_bounds__(256) void k_lists(
   }
   if (a.first_up) {
     const uint32_t set = (uint32_t)((uint64_t)pkey[p] >> (3 * (a.level - 1)));
-    base = a.first_cur[set];
     upbase = a.first_up[set];
     if (a.up_all) cnt = a.first_up[set + 1] - upbase;
     if (a.set_level[set] < a.level) cnt = 0;  // the set's lists stop above this level
   }
   const uint32_t rmask = a.recv_mask_up[p];
   const uint32_t rfirst = a.recv_child_up[p];
-  uint32_t m = 0, cb = 0, wa = 0, wb = 0;
-  uint32_t ax0 = 0, ax1 = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
+  uint32_t wa = 0, wb = 0;
   if (j < cnt) {
     const uint32_t s = upbase + (a.up_all ? j : a.e2_ent_up[j0 + j]);
     const A sk = (A)skey[s], pk = (A)pkey[p];
@@ -107,17 +107,16 @@ __global__ __launch_bounds__(256) void k_lists(
     const int dx = axis_delta<A>(sk, pk, X, (A)1);
     const int dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
     const int dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
-    m = a.src_mask_up[s];
-    if (MODE == 1) cb = a.src_child_up[s] - base;
+    const uint32_t m = a.src_mask_up[s];
     // Children of s adjacent to a receiver child whose axis bit is 0 / 1:
     // offset 0: all; +1: child bit 0 and receiver bit 1; -1: child bit 1 and
     // receiver bit 0. Octants with the x / y / z bit clear: 0x55 / 0x33 / 0x0F.
-    ax0 = dx == 0 ? 0xFFu : (dx < 0 ? 0xAAu : 0u);
-    ax1 = dx == 0 ? 0xFFu : (dx > 0 ? 0x55u : 0u);
-    ay0 = dy == 0 ? 0xFFu : (dy < 0 ? 0xCCu : 0u);
-    ay1 = dy == 0 ? 0xFFu : (dy > 0 ? 0x33u : 0u);
-    az0 = dz == 0 ? 0xFFu : (dz < 0 ? 0xF0u : 0u);
-    az1 = dz == 0 ? 0xFFu : (dz > 0 ? 0x0Fu : 0u);
+    const uint32_t ax0 = dx == 0 ? 0xFFu : (dx < 0 ? 0xAAu : 0u);
+    const uint32_t ax1 = dx == 0 ? 0xFFu : (dx > 0 ? 0x55u : 0u);
+    const uint32_t ay0 = dy == 0 ? 0xFFu : (dy < 0 ? 0xCCu : 0u);
+    const uint32_t ay1 = dy == 0 ? 0xFFu : (dy > 0 ? 0x33u : 0u);
+    const uint32_t az0 = dz == 0 ? 0xFFu : (dz < 0 ? 0xF0u : 0u);
+    const uint32_t az1 = dz == 0 ? 0xFFu : (dz > 0 ? 0x0Fu : 0u);
     wa = (uint32_t)__popc(m);
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
@@ -129,161 +128,270 @@ __global__ __launch_bounds__(256) void k_lists(
   }
   // Each field's sum over the half-wave stays in range: all children <= 216,
   // E2 of one octant <= 27.
-  const uint32_t ia = half_incl_scan(wa), ib = half_incl_scan(wb);
-  const uint32_t ea = ia - wa, eb = ib - wb;
-  const uint32_t ta = __shfl(ia, 31, 32), tb = __shfl(ib, 31, 32);
-  // Offsets of p's receiver children, loaded up front (lane k holds child k)
-  // so that no load sits inside the loop below: on this GPU a wait for a load
-  // also waits for every store issued before it.
-  const uint32_t nchild = __popc(rmask);
-  uint32_t my_o2 = 0, my_o4 = 0;
-  if (MODE == 1 && j < nchild) {
-    my_o2 = off2[rfirst + j];
-    my_o4 = off4[rfirst + j];
-  }
-  uint32_t* buf = s_buf[MODE == 1 ? h : 0];
+  const uint32_t ta = __shfl(half_incl_scan(wa), 31, 32);
+  const uint32_t tb = __shfl(half_incl_scan(wb), 31, 32);
   uint32_t k = 0;
   uint32_t qm = rmask;
 #pragma unroll 1
   while (qm) {
     const uint32_t q = __builtin_ctz(qm);
     qm &= qm - 1;
-    const uint32_t n2 = octant_field(ta, tb, q), n4 = (ta & 0xFFu) - n2;
-    if (MODE == 0) {
-      if (j == 0) {
-        cnt2[rfirst + k] = n2;
-        cnt4[rfirst + k] = n4;
-      }
-    } else {
-      const uint32_t o2 = __shfl(my_o2, k, 32), o4 = __shfl(my_o4, k, 32);
-      const uint32_t adj = ((q & 1u) ? ax1 : ax0) & ((q & 2u) ? ay1 : ay0) & ((q & 4u) ? az1 : az0);
-      const uint32_t b2 = kE2At + octant_field(ea, eb, q);
-      const uint32_t b4 = (ea & 0xFFu) - octant_field(ea, eb, q);
-      const uint32_t e2b = m & adj, e4b = m & ~adj;
-      // Child octant o of s: rank cb + (children of s below o); it goes to E2
-      // after the E2 children below it, else to E4 after the E4 ones below it.
-#pragma unroll
-      for (uint32_t o = 0; o < 8; ++o) {
-        const uint32_t below = (1u << o) - 1u;
-        if (m & (1u << o)) {
-          const uint32_t pos = (adj & (1u << o)) ? b2 + __popc(e2b & below)
-                                                 : b4 + __popc(e4b & below);
-          buf[pos] = cb + __popc(m & below);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      uint32_t v4[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const uint32_t idx = j + 32u * i;
-        v4[i] = idx < n4 ? buf[idx] : 0u;
-      }
-      const uint32_t v2 = j < n2 ? buf[kE2At + j] : 0u;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const uint32_t idx = j + 32u * i;
-        if (idx < n4) ent4[(uint64_t)o4 + idx] = v4[i];
-      }
-      if (j < n2) ent2[(uint64_t)o2 + j] = v2;
-      __builtin_amdgcn_wave_barrier();
+    if (j == 0) {
+      const uint32_t n2 = octant_field(ta, tb, q);
+      cnt2[rfirst + k] = n2;
+      cnt4[rfirst + k] = (ta & 0xFFu) - n2;
     }
     ++k;
   }
 }
 
-template <int MODE>
-void launch_lists(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
-                  const uint32_t* off2, const uint32_t* off4, uint32_t* ent2, uint32_t* ent4,
-                  hipStream_t s) {
-  if (a.n_recv_up == 0) return;  // with n_recv_up_dev: the capacity
-  const uint32_t grid = div_up(a.n_recv_up, 8);
-  const bool narrow = a.key_bits_up <= 32;  // parent-level keys fit 32 bits
-  if (key64 && narrow)
-    hipLaunchKernelGGL((k_lists<uint64_t, uint32_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
-                       cnt4, off2, off4, ent2, ent4);
-  else if (key64)
-    hipLaunchKernelGGL((k_lists<uint64_t, uint64_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
-                       cnt4, off2, off4, ent2, ent4);
-  else
-    hipLaunchKernelGGL((k_lists<uint32_t, uint32_t, MODE>), dim3(grid), dim3(256), 0, s, a, cnt2,
-                       cnt4, off2, off4, ent2, ent4);
+template <typename KeyT, typename A>
+__global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32_t* __restrict__ off2,
+                                                   const uint32_t* __restrict__ off4,
+                                                   uint32_t* __restrict__ ent2,
+                                                   uint32_t* __restrict__ ent4) {
+  __shared__ uint32_t s_rank[8][kUnion];
+  __shared__ uint8_t s_adj[8][kUnion];
+  const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
+  const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
+  const uint32_t lane = threadIdx.x & 63u, j = lane & 31u, h = threadIdx.x >> 5;
+  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  const uint32_t n_up = a.n_recv_up_dev ? *a.n_recv_up_dev : a.n_recv_up;
+  if ((uint64_t)blockIdx.x * 8 + (h & ~1u) >= n_up) return;  // whole wave: both parents absent
+  const bool live = p < n_up;
+  // Setup, one half-wave per parent p (lane j: the j-th entry s of E2(p)).
+  // upbase: batch rank of the set's first box at level - 1 (parent-level E2
+  // entries are stored relative to it); base: the same at level l.
+  uint32_t j0 = 0, cnt = 0, upbase = 0, base = 0, rmask = 0, rfirst = 0;
+  if (live) {
+    if (a.up_all) {
+      cnt = a.n_src_up;
+    } else {
+      j0 = a.e2_off_up[p];
+      cnt = a.e2_off_up[p + 1] - j0;
+    }
+    if (a.first_up) {
+      const uint32_t set = (uint32_t)((uint64_t)pkey[p] >> (3 * (a.level - 1)));
+      base = a.first_cur[set];
+      upbase = a.first_up[set];
+      if (a.up_all) cnt = a.first_up[set + 1] - upbase;
+      if (a.set_level[set] < a.level) cnt = 0;  // the set's lists stop above this level
+    }
+    rmask = a.recv_mask_up[p];
+    rfirst = a.recv_child_up[p];
+  }
+  // Offsets of p's receiver children (lane j holds child j), loaded before
+  // any store: on this GPU a wait for a load also waits for earlier stores.
+  uint32_t my_o2 = 0, my_o4 = 0;
+  if (j < (uint32_t)__popc(rmask)) {
+    my_o2 = off2[rfirst + j];
+    my_o4 = off4[rfirst + j];
+  }
+  uint32_t m = 0, cb = 0, xm0 = 0, xm1 = 0, ym0 = 0, ym1 = 0, zm0 = 0, zm1 = 0;
+  if (j < cnt) {
+    const uint32_t s = upbase + (a.up_all ? j : a.e2_ent_up[j0 + j]);
+    const A sk = (A)skey[s], pk = (A)pkey[p];
+    const A X = (A)kAxisX;
+    const int dx = axis_delta<A>(sk, pk, X, (A)1);
+    const int dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
+    const int dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
+    m = a.src_mask_up[s];
+    cb = a.src_child_up[s] - base;
+    // Receiver octants a child with axis bit 0 / 1 is adjacent to, per axis:
+    // offset 0: all; +1 (s above p on the axis): a child with bit 0 touches
+    // the receivers with bit 1; -1: a child with bit 1 touches the receivers
+    // with bit 0. Receivers with the x / y / z bit set: 0xAA / 0xCC / 0xF0.
+    xm0 = dx == 0 ? 0xFFu : (dx > 0 ? 0xAAu : 0u);
+    xm1 = dx == 0 ? 0xFFu : (dx < 0 ? 0x55u : 0u);
+    ym0 = dy == 0 ? 0xFFu : (dy > 0 ? 0xCCu : 0u);
+    ym1 = dy == 0 ? 0xFFu : (dy < 0 ? 0x33u : 0u);
+    zm0 = dz == 0 ? 0xFFu : (dz > 0 ? 0xF0u : 0u);
+    zm1 = dz == 0 ? 0xFFu : (dz < 0 ? 0x0Fu : 0u);
+  }
+  const uint32_t c = (uint32_t)__popc(m);
+  const uint32_t incl = half_incl_scan(c);
+  const uint32_t total = __shfl(incl, 31, 32);  // |U| of this half's parent, <= 216
+  {
+    uint32_t* U = s_rank[h];
+    uint8_t* ADJ = s_adj[h];
+    const uint32_t pos = incl - c;
+#pragma unroll
+    for (uint32_t o = 0; o < 8; ++o) {
+      if (m & (1u << o)) {
+        const uint32_t r = (uint32_t)__popc(m & ((1u << o) - 1u));
+        U[pos + r] = cb + r;
+        ADJ[pos + r] = (uint8_t)(((o & 1u) ? xm1 : xm0) & ((o & 2u) ? ym1 : ym0) &
+                                 ((o & 4u) ? zm1 : zm0));
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // Split, the whole wave on one parent at a time.
+#pragma unroll
+  for (uint32_t hh = 0; hh < 2; ++hh) {
+    const uint32_t T = (uint32_t)__builtin_amdgcn_readlane(total, 32 * hh);
+    const uint32_t* U = s_rank[(h & ~1u) + hh];
+    const uint8_t* ADJ = s_adj[(h & ~1u) + hh];
+    uint32_t u[4], ad = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t idx = 64u * k + lane;
+      u[k] = idx < T ? U[idx] : 0u;
+      ad |= (idx < T ? (uint32_t)ADJ[idx] : 0u) << (8 * k);
+    }
+    const uint32_t n_chunks = (T + 63u) >> 6;
+    uint32_t qm = (uint32_t)__builtin_amdgcn_readlane(rmask, 32 * hh), child = 32 * hh;
+#pragma unroll 1
+    while (qm) {
+      const uint32_t q = __builtin_ctz(qm);
+      qm &= qm - 1;
+      // next free slot of each list (wave-uniform)
+      uint32_t* d2 = ent2 + (uint32_t)__builtin_amdgcn_readlane(my_o2, child);
+      uint32_t* d4 = ent4 + (uint32_t)__builtin_amdgcn_readlane(my_o4, child);
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        if (k < n_chunks) {
+          const uint32_t rem = T - 64u * k;  // valid lanes: 0 .. rem - 1
+          const bool is2 = (ad >> (8 * k + q)) & 1u;  // 0 on invalid lanes
+          const uint64_t b2 = __ballot(is2);
+          const uint32_t i2 = mbcnt(b2);
+          // E2 lanes go to d2 in order; the other valid lanes (a prefix of
+          // the wave minus the E2 lanes) go to d4 in order.
+          uint32_t* dst = is2 ? d2 + i2 : d4 + (lane - i2);
+          if (lane < rem) *dst = u[k];
+          const uint32_t n2 = (uint32_t)__popcll(b2);
+          d2 += n2;
+          d4 += min(rem, 64u) - n2;
+        }
+      }
+      ++child;
+    }
+  }
 }
 
 void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                        hipStream_t s) {
-  launch_lists<0>(key64, a, cnt2, cnt4, nullptr, nullptr, nullptr, nullptr, s);
+  if (a.n_recv_up == 0) return;  // with n_recv_up_dev: the capacity
+  const uint32_t grid = div_up(a.n_recv_up, 8);
+  const bool narrow = a.key_bits_up <= 32;  // parent-level keys fit 32 bits
+  if (key64 && narrow)
+    hipLaunchKernelGGL((k_list_count<uint64_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4);
+  else if (key64)
+    hipLaunchKernelGGL((k_list_count<uint64_t, uint64_t>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4);
+  else
+    hipLaunchKernelGGL((k_list_count<uint32_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, cnt2,
+                       cnt4);
 }
 
 void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
                       const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s) {
-  launch_lists<1>(key64, a, nullptr, nullptr, off2, off4, ent2, ent4, s);
+  if (a.n_recv_up == 0) return;
+  const uint32_t grid = div_up(a.n_recv_up, 8);
+  const bool narrow = a.key_bits_up <= 32;
+  if (key64 && narrow)
+    hipLaunchKernelGGL((k_list_fill<uint64_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, off2,
+                       off4, ent2, ent4);
+  else if (key64)
+    hipLaunchKernelGGL((k_list_fill<uint64_t, uint64_t>), dim3(grid), dim3(256), 0, s, a, off2,
+                       off4, ent2, ent4);
+  else
+    hipLaunchKernelGGL((k_list_fill<uint32_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, off2,
+                       off4, ent2, ent4);
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of per-box list lengths into CSR offsets (the scan that
-// turns NumRecvE2NeiNEBox into NeighborBookmark, Algorithm 4), single pass.
-// off[n] = total; the total also goes to *total, and the overflow flag is set
-// if it does not fit 32-bit offsets.
+// Exclusive scans of the per-box E2 and E4 list lengths into CSR offsets (the
+// scan that turns NumRecvE2NeiNEBox into NeighborBookmark, Algorithm 4), both
+// in one single pass. off[n] = total; the totals also go to total[0..1], and
+// the overflow flag is set if a total does not fit 32-bit offsets. Wave 0
+// chains the E2 sums across tiles, wave 1 the E4 sums, at the same time.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kCompBlock) void k_scan_counts(
-    const uint32_t* __restrict__ cnt, uint32_t n_host, const uint32_t* __restrict__ n_dev,
-    uint32_t* __restrict__ off, uint64_t* __restrict__ total, uint32_t* __restrict__ overflow,
-    uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter) {
-  __shared__ uint32_t s_w[kCompBlock / 64];
-  __shared__ uint64_t s_excl;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kCompBlock * kScanItems;  // 4096 boxes
+
+__global__ __launch_bounds__(kCompBlock) void k_scan_counts2(
+    const uint32_t* __restrict__ cnt2, const uint32_t* __restrict__ cnt4, uint32_t n_host,
+    const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ off2, uint32_t* __restrict__ off4,
+    uint64_t* __restrict__ total2, uint64_t* __restrict__ total4, uint32_t* __restrict__ overflow,
+    uint64_t* __restrict__ status2, uint64_t* __restrict__ status4,
+    uint32_t* __restrict__ tile_counter) {
+  __shared__ uint32_t s_w[2][kCompBlock / 64];
+  __shared__ uint64_t s_excl[2];
   __shared__ uint32_t s_tile;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
-  if ((uint64_t)tile * kCompTile >= n) return;  // whole block: surplus tile
-  const uint64_t base = (uint64_t)tile * kCompTile + (uint64_t)tid * kCompItems;
-  uint32_t v[kCompItems];
-  uint32_t sum = 0;
+  if ((uint64_t)tile * kScanTile >= n) return;  // whole block: surplus tile
+  const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)tid * kScanItems;
+  uint32_t v2[kScanItems], v4[kScanItems];
+  uint32_t sum2 = 0, sum4 = 0;
 #pragma unroll
-  for (int i = 0; i < kCompItems; ++i) {
-    v[i] = base + i < n ? cnt[base + i] : 0;
-    sum += v[i];
+  for (int i = 0; i < kScanItems; ++i) {
+    const bool ok = base + i < n;
+    v2[i] = ok ? cnt2[base + i] : 0;
+    v4[i] = ok ? cnt4[base + i] : 0;
+    sum2 += v2[i];
+    sum4 += v4[i];
   }
-  const uint32_t inc = wave_incl_scan(sum);
-  if (lane == 63) s_w[w] = inc;
+  const uint32_t inc2 = wave_incl_scan(sum2), inc4 = wave_incl_scan(sum4);
+  if (lane == 63) {
+    s_w[0][w] = inc2;
+    s_w[1][w] = inc4;
+  }
   __syncthreads();
-  uint32_t wpre = 0, ttot = 0;
+  uint32_t wpre2 = 0, wpre4 = 0, tot2 = 0, tot4 = 0;
   for (uint32_t i = 0; i < kCompBlock / 64; ++i) {
-    if (i < w) wpre += s_w[i];
-    ttot += s_w[i];
+    if (i < w) {
+      wpre2 += s_w[0][i];
+      wpre4 += s_w[1][i];
+    }
+    tot2 += s_w[0][i];
+    tot4 += s_w[1][i];
   }
   if (w == 0) {
-    const uint64_t ex = lookback_wave(status, tile, ttot);
-    if (lane == 0) s_excl = ex;
+    const uint64_t ex = lookback_wave(status2, tile, tot2);
+    if (lane == 0) s_excl[0] = ex;
+  } else if (w == 1) {
+    const uint64_t ex = lookback_wave(status4, tile, tot4);
+    if (lane == 0) s_excl[1] = ex;
   }
   __syncthreads();
-  uint64_t pre = s_excl + wpre + inc - sum;
+  uint64_t pre2 = s_excl[0] + wpre2 + inc2 - sum2;
+  uint64_t pre4 = s_excl[1] + wpre4 + inc4 - sum4;
   bool ovf = false;
 #pragma unroll
-  for (int i = 0; i < kCompItems; ++i) {
+  for (int i = 0; i < kScanItems; ++i) {
     if (base + i < n) {
-      off[base + i] = (uint32_t)pre;
-      ovf |= pre > 0xFFFFFFFFull;
-      pre += v[i];
+      off2[base + i] = (uint32_t)pre2;
+      off4[base + i] = (uint32_t)pre4;
+      pre2 += v2[i];
+      pre4 += v4[i];
       if (base + i + 1 == n) {
-        off[n] = (uint32_t)pre;
-        *total = pre;
-        ovf |= pre > 0xFFFFFFFFull;
+        off2[n] = (uint32_t)pre2;
+        off4[n] = (uint32_t)pre4;
+        *total2 = pre2;
+        *total4 = pre4;
       }
     }
   }
+  ovf = (pre2 > 0xFFFFFFFFull) || (pre4 > 0xFFFFFFFFull);
   if (ovf) atomicOr(overflow, 1u);
 }
 
-void launch_scan_counts(const uint32_t* cnt, uint32_t n, uint32_t* off, uint64_t* total,
-                        uint32_t* overflow, uint64_t* status, uint32_t* tile_counter,
-                        hipStream_t s, const uint32_t* n_dev) {
+uint32_t scan_tiles(uint32_t n) { return div_up(n, kScanTile); }
+
+void launch_scan_counts2(const uint32_t* cnt2, const uint32_t* cnt4, uint32_t n, uint32_t* off2,
+                         uint32_t* off4, uint64_t* total2, uint64_t* total4, uint32_t* overflow,
+                         uint64_t* status2, uint64_t* status4, uint32_t* tile_counter,
+                         hipStream_t s, const uint32_t* n_dev) {
   // n is the exact count, or with n_dev the capacity (the count is read there)
   if (n == 0) return;
-  hipLaunchKernelGGL(k_scan_counts, dim3(div_up(n, kCompTile)), dim3(kCompBlock), 0, s, cnt, n,
-                     n_dev, off, total, overflow, status, tile_counter);
+  hipLaunchKernelGGL(k_scan_counts2, dim3(scan_tiles(n)), dim3(kCompBlock), 0, s, cnt2, cnt4, n,
+                     n_dev, off2, off4, total2, total4, overflow, status2, status4, tile_counter);
 }
 
 }  // namespace fmmds

@@ -95,19 +95,30 @@ void* cache_alloc(size_t bytes, hipStream_t stream) {
     std::lock_guard<std::mutex> g(g_cache_mu);
     auto& m = g_cache[dev];
     auto best = m.end();
-    // any cached block of the same class or up to twice the size
+    // A cached block of the same class or up to twice the size: first one
+    // released on this stream (stream order makes it safe), else one whose
+    // last user has finished. A block still in use on another stream is not
+    // taken: waiting for it would serialize independent streams.
+    int probed = 0;
     for (auto it = m.lower_bound(bytes); it != m.end() && it->first <= 2 * bytes; ++it) {
       if (it->second.stream == stream) {
         best = it;
         break;
       }
-      if (best == m.end()) best = it;
+      if (best != m.end() || probed >= 8) continue;
+      ++probed;
+      const CachedBlock& c = it->second;
+      if (!c.ready || !c.ready->ev) {
+        best = it;
+        continue;
+      }
+      const hipError_t q = hipEventQuery(c.ready->ev);
+      if (q == hipSuccess) best = it;
+      else (void)hipGetLastError();
     }
     if (best != m.end()) {
       CachedBlock b = best->second;
       m.erase(best);
-      if (b.stream != stream && b.ready && b.ready->ev)
-        ck(hipStreamWaitEvent(stream, b.ready->ev, 0));
       g_live[b.p] = b.bytes;
       ++g_cache_hits;
       return b.p;
@@ -511,7 +522,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       // ---- keys and sort
       uint32_t* h = hist + s * kMaxPasses * 256;
       uint32_t* g = goff + s * kMaxPasses * 256;
-      P.run(K_KEYGEN, (double)n * (12 + 8 + (packed ? 0 : 4)), [&] {
+      P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
         launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
       });
       P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
@@ -521,8 +532,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
         uint32_t* tk = sa.take_ticket();
         P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
-          launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,
-                           stw, tk, st, kSortItemsDefault);
+          launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256, stw,
+                           tk, st, kSortItemsDefault);
         });
       }
       const int fin = n_pass & 1;
@@ -534,8 +545,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         // sorted pairs in, permutation + gathered and written coordinates out;
         // leaf keys and bookmarks are added once the box count is known
         P.run(K_LEAF, (double)n * ((packed ? 8 : 12) + 4 + 12 + 12), [&] {
-          launch_leaf(packed, key64, sb.k[fin], sb.v[fin], S.xyz, n, S.perm, S.sorted_xyz,
-                      S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L], st);
+          launch_leaf(packed, key64, sb.k[fin], sb.v[fin], S.xyz, n, S.perm,
+                      S.sorted_xyz, S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L],
+                      st);
         }, s, (int)L);
       }
       for (int l = (int)L - 1; l >= 0; --l) {
@@ -580,7 +592,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // ---- lists, levels 2..D
     size_t lwords = 0, lmax = 0;
     for (uint32_t l = 2; l <= D; ++l) {
-      lwords += 2 * (size_t)div_up(nb[rs][l], kCompTile);
+      lwords += 2 * (size_t)scan_tiles(nb[rs][l]);
       lmax = std::max<size_t>(lmax, nb[rs][l]);
     }
     const size_t ltick_b = round_up(2 * (kMaxLevel + 1) * 4, 256);
@@ -618,13 +630,15 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
       P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + nr, st); });
-      for (int k = 0; k < 2; ++k) {
-        LB.off[k] = impl->outs.get<uint32_t>((size_t)nr + 1);
-        uint64_t* stw = la.take_words(div_up(nr, kCompTile));
+      LB.off[0] = impl->outs.get<uint32_t>((size_t)nr + 1);
+      LB.off[1] = impl->outs.get<uint32_t>((size_t)nr + 1);
+      {
+        uint64_t* st2 = la.take_words(scan_tiles(nr));
+        uint64_t* st4 = la.take_words(scan_tiles(nr));
         uint32_t* tk = la.take_ticket();
-        P.run(K_SCAN, (double)nr * 8 + 4, [&] {
-          launch_scan_counts(cnt + (size_t)k * nr, nr, LB.off[k], &meta->list_total[k][l],
-                             &meta->overflow, stw, tk, st);
+        P.run(K_SCAN, (double)nr * 16 + 8, [&] {
+          launch_scan_counts2(cnt, cnt + nr, nr, LB.off[0], LB.off[1], &meta->list_total[0][l],
+                              &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st);
         });
       }
       fetch_meta(meta, hm, st);  // sync point: this level's list totals
@@ -820,14 +834,26 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
   P.run(K_REBASE, 0.0, [&] {
     launch_batch_first(lp, L, meta->n_boxes[0], B.d_off, B.n_sets, B.first(), st);
   });
-  for (uint32_t l = 0; l <= L; ++l) {
-    P.run(K_REBASE, 0.0, [&] {
-      launch_batch_rebase(l, B.cap[l], &meta->n_boxes[0][l], (const uint64_t*)B.g[l].key,
-                          B.g[l].begin, l >= 1 ? B.g[l].parent : nullptr,
-                          l < L ? B.g[l].child : nullptr, l >= 1 ? B.first_l(l - 1) : nullptr,
-                          B.first_l(l), l < L ? B.first_l(l + 1) : nullptr, B.d_off, B.fkey[l],
-                          B.fbegin[l], B.fparent[l], B.fchild[l], st);
-    });
+  uint32_t max_cap = 1;
+  for (uint32_t l = 0; l <= L; ++l) max_cap = std::max(max_cap, B.cap[l]);
+  {
+    RebaseArgs ra{};
+    for (uint32_t l = 0; l <= L; ++l) {
+      ra.n_l[l] = &meta->n_boxes[0][l];
+      ra.gkey[l] = (const uint64_t*)B.g[l].key;
+      ra.gbegin[l] = B.g[l].begin;
+      ra.gparent[l] = l >= 1 ? B.g[l].parent : nullptr;
+      ra.gchild[l] = l < L ? B.g[l].child : nullptr;
+      ra.fkey[l] = B.fkey[l];
+      ra.fbegin[l] = B.fbegin[l];
+      ra.fparent[l] = B.fparent[l];
+      ra.fchild[l] = B.fchild[l];
+    }
+    ra.first = B.first();
+    ra.set_off = B.d_off;
+    ra.n_sets = B.n_sets;
+    ra.L = L;
+    P.run(K_REBASE, 0.0, [&] { launch_batch_rebase(ra, max_cap, st); });
   }
   for (uint32_t l = 2; l <= L; ++l) {
     ListLevelArgs a{};
@@ -852,22 +878,35 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
     uint32_t* c2 = B.cnt;
     uint32_t* c4 = B.cnt + B.cap[l];
     P.run(K_COUNT, 0.0, [&] { launch_list_count(true, a, c2, c4, st); });
-    for (int k = 0; k < 2; ++k) {
-      uint64_t* stw = sa.take_words(div_up(B.cap[l], kCompTile));
+    {
+      uint64_t* st2 = sa.take_words(scan_tiles(B.cap[l]));
+      uint64_t* st4 = sa.take_words(scan_tiles(B.cap[l]));
       uint32_t* tk = sa.take_ticket();
       P.run(K_SCAN, 0.0, [&] {
-        launch_scan_counts(k == 0 ? c2 : c4, B.cap[l], B.goff[l][k], &meta->list_total[k][l],
-                           &meta->overflow, stw, tk, st, &meta->n_boxes[0][l]);
+        launch_scan_counts2(c2, c4, B.cap[l], B.goff[l][0], B.goff[l][1], &meta->list_total[0][l],
+                            &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st,
+                            &meta->n_boxes[0][l]);
       });
     }
     P.run(K_FILL, 0.0, [&] {
       launch_list_fill(true, a, B.goff[l][0], B.goff[l][1], B.ent[l][0], B.ent[l][1], st);
     });
-    P.run(K_REBASE, 0.0, [&] {
-      launch_batch_list_rebase(l, B.cap[l], &meta->n_boxes[0][l], (const uint64_t*)B.g[l].key,
-                               B.first_l(l), B.goff[l][0], B.goff[l][1], B.loff[l][0],
-                               B.loff[l][1], B.base(l, 0), B.base(l, 1), B.n_sets, st);
-    });
+  }
+  {
+    ListRebaseArgs la{};
+    for (uint32_t l = 2; l <= L; ++l) {
+      la.n_l[l] = &meta->n_boxes[0][l];
+      la.gkey[l] = (const uint64_t*)B.g[l].key;
+      la.goff2[l] = B.goff[l][0];
+      la.goff4[l] = B.goff[l][1];
+      la.loff2[l] = B.loff[l][0];
+      la.loff4[l] = B.loff[l][1];
+    }
+    la.first = B.first();
+    la.base = B.base(0, 0);
+    la.n_sets = B.n_sets;
+    la.L = L;
+    P.run(K_REBASE, 0.0, [&] { launch_batch_list_rebase(la, max_cap, st); });
   }
   ck(hipMemcpyAsync(B.hblock, B.dblock, B.dblock_b, hipMemcpyDeviceToHost, st));
 }
@@ -912,13 +951,25 @@ int batch_autotune(BatchImpl& B, const float* xyz) {
   return best;
 }
 
-fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
-                          const fmmds_options* opt, fmmds_batch** out) {
-  if (!set_offsets || !levels || !opt || n_sets == 0) return FMMDS_ERR_ARG;
-  if (opt->key_bits != 64 || opt->cluster_s != 0 || opt->reserved != 0 ||
-      ((opt->alloc == nullptr) != (opt->release == nullptr)))
-    return FMMDS_ERR_ARG;
-  if (set_offsets[0] != 0) return FMMDS_ERR_ARG;
+// Sub-allocation of one block; with base == nullptr it only measures.
+struct Carve {
+  char* base = nullptr;
+  size_t used = 0;
+  template <typename T>
+  T* get(size_t count) {
+    const size_t b = round_up(std::max<size_t>(count * sizeof(T), 1), 256);
+    T* p = base ? (T*)(base + used) : nullptr;
+    used += b;
+    return p;
+  }
+};
+
+// Validates the shape and fills the scalar plan: levels, key width, passes
+// and per-level capacities (boxes of set i at level l are at most
+// min(n_i, 8^min(l, L_i))).
+fmmds_status batch_plan(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
+                        BatchImpl& B) {
+  if (!set_offsets || !levels || n_sets == 0 || set_offsets[0] != 0) return FMMDS_ERR_ARG;
   uint32_t L = 0;
   for (uint32_t i = 0; i < n_sets; ++i) {
     if (set_offsets[i + 1] <= set_offsets[i]) return FMMDS_ERR_ARG;
@@ -929,18 +980,102 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
   uint32_t setbits = 1;
   while ((1ull << setbits) < n_sets) ++setbits;
   if (setbits + 3 * L > 64) return FMMDS_ERR_ARG;
+  B.n_sets = n_sets;
+  B.P = (uint32_t)set_offsets[n_sets];
+  B.L = L;
+  B.setbits = setbits;
+  B.keybits = setbits + 3 * L;
+  B.packed = B.keybits <= 32;
+  B.n_pass = div_up(B.keybits, 8);
+  for (uint32_t l = 0; l <= L; ++l) {
+    uint64_t c = 0, r = 0;
+    for (uint32_t i = 0; i < n_sets; ++i) {
+      const uint64_t ni = set_offsets[i + 1] - set_offsets[i];
+      const uint32_t e = std::min<uint32_t>(l, levels[i]);
+      const uint64_t boxes = std::min<uint64_t>(ni, 1ull << (3 * e));
+      c += boxes;
+      if (levels[i] >= l) r += boxes;
+    }
+    B.cap[l] = (uint32_t)c;
+    B.rcap[l] = (uint32_t)r;
+    if (l >= 2 && 189ull * r > 0xFFFFFFFFull) return FMMDS_ERR_OVERFLOW;
+  }
+  return FMMDS_OK;
+}
 
+// Every device buffer of a planned batch, carved from one block.
+void batch_layout(BatchImpl& B, Carve& M) {
+  const uint32_t n_sets = B.n_sets, P = B.P, L = B.L;
+  B.d_off = M.get<uint64_t>(n_sets + 1);
+  B.d_lev = M.get<uint8_t>(n_sets);
+  B.sb.k[0] = M.get<uint64_t>(P);
+  B.sb.k[1] = M.get<uint64_t>(P);
+  B.sb.v[0] = B.sb.v[1] = nullptr;
+  if (!B.packed) {
+    B.sb.v[0] = M.get<uint32_t>(P);
+    B.sb.v[1] = M.get<uint32_t>(P);
+  }
+  B.perm = M.get<uint32_t>(P);
+  B.sxyz = M.get<float>(3 * (size_t)P);
+  uint32_t cmax = 0;
+  for (uint32_t l = 0; l <= L; ++l) {
+    const size_t c = B.cap[l];
+    cmax = std::max<uint32_t>(cmax, (uint32_t)c);
+    LevelBufs& G = B.g[l];
+    G = LevelBufs();
+    G.cap = (uint32_t)c;
+    G.key = M.get<uint64_t>(c);
+    G.begin = M.get<uint32_t>(c + 1);
+    if (l >= 1) G.parent = M.get<uint32_t>(c);
+    if (l < L) {
+      G.child = M.get<uint32_t>(c + 1);
+      G.mask = M.get<uint8_t>(c);
+    }
+    B.fkey[l] = M.get<uint64_t>(c);
+    B.fbegin[l] = M.get<uint32_t>(c + n_sets);
+    B.fparent[l] = l >= 1 ? M.get<uint32_t>(c) : nullptr;
+    B.fchild[l] = l < L ? M.get<uint32_t>(c + n_sets) : nullptr;
+    if (l >= 2) {
+      for (int k = 0; k < 2; ++k) {
+        B.goff[l][k] = M.get<uint32_t>(c + 1);
+        B.loff[l][k] = M.get<uint32_t>(c + n_sets);
+        B.ent[l][k] = M.get<uint32_t>((size_t)(k == 0 ? 27 : 189) * B.rcap[l]);
+      }
+    }
+  }
+  B.cnt = M.get<uint32_t>(2 * (size_t)std::max<uint32_t>(cmax, 1));
+  // metadata block and the zeroed workspace around it
+  B.first_at = round_up(sizeof(DevMeta), 256);
+  B.base_at = round_up(B.first_at + (size_t)(L + 1) * (n_sets + 1) * 4, 256);
+  B.dblock_b = round_up(B.base_at + (size_t)(L + 1) * 2 * (n_sets + 1) * 4, 256);
+  B.hist_at = B.dblock_b;
+  B.goffd_at = B.hist_at + round_up(kMaxPasses * 256 * 4, 256);
+  B.tick_at = B.goffd_at + round_up(kMaxPasses * 256 * 4, 256);
+  B.n_tickets = B.n_pass + 1 + L + 2 * (L + 1);
+  B.words_at = B.tick_at + round_up(B.n_tickets * 4, 256);
+  size_t words = (size_t)B.n_pass * sort_tiles(P, 8) * 256 + div_up(P, kCompTile);
+  for (uint32_t l = 0; l < L; ++l) words += div_up(B.cap[l + 1], kCompTile);
+  for (uint32_t l = 2; l <= L; ++l) words += 2 * (size_t)scan_tiles(B.cap[l]);
+  B.n_words = words;
+  B.ws_b = round_up(B.words_at + words * 8, 256);
+  B.ws = M.get<char>(B.ws_b);
+  B.dblock = B.ws;
+}
+
+fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
+                          const fmmds_options* opt, fmmds_batch** out) {
+  if (!set_offsets || !levels || !opt || n_sets == 0) return FMMDS_ERR_ARG;
+  if (opt->key_bits != 64 || opt->cluster_s != 0 || opt->reserved != 0 ||
+      ((opt->alloc == nullptr) != (opt->release == nullptr)))
+    return FMMDS_ERR_ARG;
   BatchImpl* B = new (std::nothrow) BatchImpl();
   if (!B) return FMMDS_ERR_NOMEM;
-  fmmds_status result = FMMDS_OK;
+  fmmds_status result = batch_plan(set_offsets, levels, n_sets, *B);
+  if (result != FMMDS_OK) {
+    delete B;
+    return result;
+  }
   try {
-    B->n_sets = n_sets;
-    B->P = (uint32_t)set_offsets[n_sets];
-    B->L = L;
-    B->setbits = setbits;
-    B->keybits = setbits + 3 * L;
-    B->packed = B->keybits <= 32;
-    B->n_pass = div_up(B->keybits, 8);
     B->off.assign(set_offsets, set_offsets + n_sets + 1);
     B->lev.assign(levels, levels + n_sets);
     if (opt->stream) {
@@ -954,74 +1089,11 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
     B->A.ctx = opt->alloc_ctx;
     B->A.stream = B->stream;
     B->mem.A = &B->A;
-    const uint32_t P = B->P;
-    // capacities: boxes of set i at level l are at most min(n_i, 8^min(l, L_i))
-    for (uint32_t l = 0; l <= L; ++l) {
-      uint64_t c = 0, r = 0;
-      for (uint32_t i = 0; i < n_sets; ++i) {
-        const uint64_t ni = set_offsets[i + 1] - set_offsets[i];
-        const uint32_t e = std::min<uint32_t>(l, levels[i]);
-        const uint64_t boxes = std::min<uint64_t>(ni, 1ull << (3 * e));
-        c += boxes;
-        if (levels[i] >= l) r += boxes;
-      }
-      B->cap[l] = (uint32_t)c;
-      B->rcap[l] = (uint32_t)r;
-      if (l >= 2 && 189ull * r > 0xFFFFFFFFull) throw Fail{FMMDS_ERR_OVERFLOW};
-    }
-    Pool& M = B->mem;
-    B->d_off = M.get<uint64_t>(n_sets + 1);
-    B->d_lev = M.get<uint8_t>(n_sets);
-    B->sb.k[0] = M.get<uint64_t>(P);
-    B->sb.k[1] = M.get<uint64_t>(P);
-    if (!B->packed) {
-      B->sb.v[0] = M.get<uint32_t>(P);
-      B->sb.v[1] = M.get<uint32_t>(P);
-    }
-    B->perm = M.get<uint32_t>(P);
-    B->sxyz = M.get<float>(3 * (size_t)P);
-    uint32_t cmax = 0;
-    for (uint32_t l = 0; l <= L; ++l) {
-      const size_t c = B->cap[l];
-      cmax = std::max<uint32_t>(cmax, (uint32_t)c);
-      LevelBufs& G = B->g[l];
-      G.cap = (uint32_t)c;
-      G.key = M.get<uint64_t>(c);
-      G.begin = M.get<uint32_t>(c + 1);
-      if (l >= 1) G.parent = M.get<uint32_t>(c);
-      if (l < L) {
-        G.child = M.get<uint32_t>(c + 1);
-        G.mask = M.get<uint8_t>(c);
-      }
-      B->fkey[l] = M.get<uint64_t>(c);
-      B->fbegin[l] = M.get<uint32_t>(c + n_sets);
-      if (l >= 1) B->fparent[l] = M.get<uint32_t>(c);
-      if (l < L) B->fchild[l] = M.get<uint32_t>(c + n_sets);
-      if (l >= 2) {
-        for (int k = 0; k < 2; ++k) {
-          B->goff[l][k] = M.get<uint32_t>(c + 1);
-          B->loff[l][k] = M.get<uint32_t>(c + n_sets);
-          B->ent[l][k] = M.get<uint32_t>((size_t)(k == 0 ? 27 : 189) * B->rcap[l]);
-        }
-      }
-    }
-    B->cnt = M.get<uint32_t>(2 * (size_t)std::max<uint32_t>(cmax, 1));
-    // metadata block and the zeroed workspace around it
-    B->first_at = round_up(sizeof(DevMeta), 256);
-    B->base_at = round_up(B->first_at + (size_t)(L + 1) * (n_sets + 1) * 4, 256);
-    B->dblock_b = round_up(B->base_at + (size_t)(L + 1) * 2 * (n_sets + 1) * 4, 256);
-    B->hist_at = B->dblock_b;
-    B->goffd_at = B->hist_at + round_up(kMaxPasses * 256 * 4, 256);
-    B->tick_at = B->goffd_at + round_up(kMaxPasses * 256 * 4, 256);
-    B->n_tickets = B->n_pass + 1 + L + 2 * (L + 1);
-    B->words_at = B->tick_at + round_up(B->n_tickets * 4, 256);
-    size_t words = (size_t)B->n_pass * sort_tiles(P, 8) * 256 + div_up(P, kCompTile);
-    for (uint32_t l = 0; l < L; ++l) words += div_up(B->cap[l + 1], kCompTile);
-    for (uint32_t l = 2; l <= L; ++l) words += 2 * (size_t)div_up(B->cap[l], kCompTile);
-    B->n_words = words;
-    B->ws_b = round_up(B->words_at + words * 8, 256);
-    B->ws = M.get<char>(B->ws_b);
-    B->dblock = B->ws;
+    Carve M;
+    batch_layout(*B, M);  // measure
+    M.base = B->mem.get<char>(M.used);
+    M.used = 0;
+    batch_layout(*B, M);  // assign
     // Pinned host block: the metadata mirror, then the offsets and levels
     // staged for an asynchronous upload (it lives as long as the batch).
     const size_t stage_off = round_up(B->dblock_b, 256);
@@ -1037,9 +1109,7 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
     B->trees.assign(n_sets, fmmds_tree());
     B->views.resize(n_sets);
     for (uint32_t i = 0; i < n_sets; ++i) B->views[i].view = true;
-    B->footprint = 0;
-    for (const Block& blk : M.blocks)
-      B->footprint += cache_round(round_up(std::max<size_t>(blk.bytes, 1), 256));
+    B->footprint = cache_round(round_up(M.used, 256));
   } catch (const Fail& f) {
     result = f.st;
   } catch (const std::bad_alloc&) {
@@ -1060,56 +1130,21 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
   return FMMDS_OK;
 }
 
-// Device bytes fmmds_batch_create would allocate for this shape (host only;
-// mirrors the allocations of batch_create, each rounded as the allocator does).
+// Device bytes fmmds_batch_create allocates for this shape (host only: the
+// same plan and layout, measured, rounded as the allocator rounds).
 fmmds_status batch_footprint(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
                              uint64_t* bytes) {
-  if (!set_offsets || !levels || !bytes || n_sets == 0 || set_offsets[0] != 0)
-    return FMMDS_ERR_ARG;
-  uint32_t L = 0;
-  for (uint32_t i = 0; i < n_sets; ++i) {
-    if (set_offsets[i + 1] <= set_offsets[i] || levels[i] < 2 || levels[i] > FMMDS_MAX_LEVEL)
-      return FMMDS_ERR_ARG;
-    L = std::max<uint32_t>(L, levels[i]);
+  if (!bytes) return FMMDS_ERR_ARG;
+  try {
+    BatchImpl B;
+    const fmmds_status st = batch_plan(set_offsets, levels, n_sets, B);
+    if (st != FMMDS_OK) return st;
+    Carve M;
+    batch_layout(B, M);
+    *bytes = cache_round(round_up(M.used, 256));
+  } catch (const std::bad_alloc&) {
+    return FMMDS_ERR_NOMEM;
   }
-  if (set_offsets[n_sets] >= 0xFFFFFFFFull) return FMMDS_ERR_ARG;
-  uint32_t setbits = 1;
-  while ((1ull << setbits) < n_sets) ++setbits;
-  if (setbits + 3 * L > 64) return FMMDS_ERR_ARG;
-  const uint64_t P = set_offsets[n_sets];
-  const bool packed = setbits + 3 * L <= 32;
-  const uint32_t n_pass = div_up(setbits + 3 * L, 8);
-  auto blk = [](uint64_t b) { return (uint64_t)cache_round(round_up(std::max<uint64_t>(b, 1), 256)); };
-  uint64_t total = blk((n_sets + 1) * 8) + blk(n_sets) + 2 * blk(8 * P) +
-                   (packed ? 0 : 2 * blk(4 * P)) + blk(4 * P) + blk(12 * P);
-  uint64_t cmax = 0, words = (uint64_t)n_pass * sort_tiles((uint32_t)P, 8) * 256 +
-                            div_up(P, kCompTile);
-  for (uint32_t l = 0; l <= L; ++l) {
-    uint64_t c = 0, r = 0;
-    for (uint32_t i = 0; i < n_sets; ++i) {
-      const uint64_t ni = set_offsets[i + 1] - set_offsets[i];
-      const uint64_t boxes = std::min<uint64_t>(ni, 1ull << (3 * std::min<uint32_t>(l, levels[i])));
-      c += boxes;
-      if (levels[i] >= l) r += boxes;
-    }
-    cmax = std::max(cmax, c);
-    total += blk(8 * c) + blk(4 * (c + 1)) + blk(8 * c) + blk(4 * (c + n_sets));
-    if (l >= 1) total += blk(4 * c) + blk(4 * c);
-    if (l < L) total += blk(4 * (c + 1)) + blk(c) + blk(4 * (c + n_sets));
-    if (l >= 2) total += 2 * (blk(4 * (c + 1)) + blk(4 * (c + n_sets))) + blk(4 * 27 * r) +
-                         blk(4 * 189 * r);
-    if (l >= 1) words += div_up(c, kCompTile);  // level l-1 from level l
-    if (l >= 2) words += 2 * (uint64_t)div_up(c, kCompTile);
-  }
-  total += blk(2 * 4 * std::max<uint64_t>(cmax, 1));
-  const uint64_t dblock = round_up(round_up(round_up(sizeof(DevMeta), 256) +
-                                            (uint64_t)(L + 1) * (n_sets + 1) * 4, 256) +
-                                       (uint64_t)(L + 1) * 2 * (n_sets + 1) * 4,
-                                   256);
-  const uint64_t tickets = n_pass + 1 + L + 2 * (L + 1);
-  total += blk(dblock + 2 * round_up(kMaxPasses * 256 * 4, 256) + round_up(tickets * 4, 256) +
-               words * 8);
-  *bytes = total;
   return FMMDS_OK;
 }
 
@@ -1305,6 +1340,28 @@ uint32_t fmmds_batch_sort_items(const fmmds_batch* b) {
 }
 
 void fmmds_batch_free(fmmds_batch* b) { fmmds::batch_free((fmmds::BatchImpl*)b); }
+
+fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, float sigma,
+                            float* out, void* stream) {
+  if (!sets || n_sets == 0) return FMMDS_ERR_ARG;
+  for (uint32_t i = 0; i < n_sets; ++i)
+    if (!sets[i].xyz || sets[i].n == 0) return FMMDS_ERR_ARG;
+  fmmds::DisplaceArgs a;
+  for (uint32_t b = 0; b < n_sets; b += fmmds::kDisplaceSets) {
+    a.n = std::min<uint32_t>(n_sets - b, fmmds::kDisplaceSets);
+    a.first[0] = 0;
+    for (uint32_t k = 0; k < a.n; ++k) {
+      const fmmds_displace_set& d = sets[b + k];
+      a.xyz[k] = d.xyz;
+      a.seed[k] = d.seed;
+      a.out_first[k] = d.out_first;
+      a.first[k + 1] = a.first[k] + d.n;
+    }
+    fmmds::launch_displace(a, sigma, out, (hipStream_t)stream);
+  }
+  if (hipGetLastError() != hipSuccess) return FMMDS_ERR_DEVICE;
+  return FMMDS_OK;
+}
 
 void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,
                       uint64_t* cached_bytes) {

@@ -147,14 +147,19 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
 
   uint64_t pkey[kCompItems];
   uint32_t incl[kCompItems];
+  uint32_t cmask[kCompItems];  // child octants of the parent a flagged box starts
   uint32_t flags = 0;
+  const uint32_t lane = tid & 63u;
 #pragma unroll
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;
     const bool valid = j < n_in;
     uint64_t pk = 0, pp = 0;
+    uint32_t oct = 8;
     if (valid) {
-      pk = (uint64_t)kin[j] >> 3;
+      const uint64_t k = (uint64_t)kin[j];
+      pk = k >> 3;
+      oct = (uint32_t)(k & 7u);
       if (j > 0) pp = (uint64_t)kin[j - 1] >> 3;
     }
     const bool f = valid && (j == 0 || pk != pp);
@@ -162,7 +167,25 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
     incl[i] = mbcnt(ball) + (f ? 1u : 0u);
     flags |= (f ? 1u : 0u) << i;
     pkey[i] = pk;
-    if ((tid & 63) == 0) s_cnt[i * kCompWaves + w] = (uint32_t)__popcll(ball);
+    if (lane == 0) s_cnt[i * kCompWaves + w] = (uint32_t)__popcll(ball);
+    // Boxes j.. up to the next flag share this parent. Consecutive lanes hold
+    // consecutive boxes, so the children inside this wave are the lanes from
+    // here to the next flagged lane: one ballot per child octant.
+    const uint64_t later = ball & ~((2ull << lane) - 1ull);  // flagged lanes above this one
+    const uint32_t end = later ? (uint32_t)(__ffsll((long long)later) - 1) : 64u;
+    const uint64_t run = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 8; ++b) m |= ((__ballot(oct == b) & run) ? 1u : 0u) << b;
+    if (f && end == 64) {
+      // the run may continue past this wave's last lane
+      for (uint64_t t = j + (64 - lane); t < n_in && t < j + 8; ++t) {
+        const uint64_t kt = (uint64_t)kin[t];
+        if ((kt >> 3) != pk) break;
+        m |= 1u << (kt & 7u);
+      }
+    }
+    cmask[i] = m;
   }
   const uint64_t texcl = tile_flags_prefix(s_cnt, &s_excl, status, tile);
 #pragma unroll
@@ -175,13 +198,7 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
       kout[rank] = (KeyT)pkey[i];
       bout[rank] = bin[j];
       cout[rank] = (uint32_t)j;
-      uint32_t m = 0;
-      for (uint64_t t = j; t < n_in && t < j + 8; ++t) {
-        const uint64_t kt = kin[t];
-        if ((kt >> 3) != pkey[i]) break;
-        m |= 1u << (kt & 7u);
-      }
-      mout[rank] = (uint8_t)m;
+      mout[rank] = (uint8_t)cmask[i];
     }
     if (j + 1 == n_in) {
       bout[rank + 1] = n_points;

@@ -25,6 +25,7 @@ GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 ONE_MINUS_ULP = np.float64(1.0 - 2.0 ** -24)
+_MASK = (1 << 64) - 1
 
 # Stream tags keep the draws of one workload independent of each other.
 TAG_POINTS = 0x01
@@ -44,14 +45,20 @@ def _mix(z: np.ndarray) -> np.ndarray:
     return z ^ (z >> np.uint64(31))
 
 
+def _mix_int(z: int) -> int:
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+    return z ^ (z >> 31)
+
+
 def stream_seed(*parts: int) -> int:
-    """Derive a 64-bit stream seed from integers (seed, tag, index, ...)."""
-    s = np.uint64(0x243F6A8885A308D3)
-    with np.errstate(over="ignore"):
-        for p in parts:
-            s = _mix(np.asarray(s ^ np.uint64(p & 0xFFFFFFFFFFFFFFFF) + GAMMA,
-                                dtype=np.uint64))
-    return int(s)
+    """Derive a 64-bit stream seed from integers (seed, tag, index, ...):
+    s <- mix(s xor (part + GAMMA)) for each part, from s = 0x243F6A8885A308D3,
+    in wrapping 64-bit arithmetic (plain Python integers, masked)."""
+    s = 0x243F6A8885A308D3
+    for p in parts:
+        s = _mix_int(s ^ (((p & _MASK) + 0x9E3779B97F4A7C15) & _MASK))
+    return s
 
 
 def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:

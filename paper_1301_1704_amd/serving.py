@@ -7,8 +7,9 @@ which particles move every time step and the structures are rebuilt each step
 on one GPU:
 
 - every request names a system; it displaces the system's points by
-  N(0, sigma^2) per coordinate (seeded by system and step, clamped into the
-  unit cube) and rebuilds its tables and lists;
+  N(0, sigma^2) per coordinate (fmmds_displace: counter-based normals seeded
+  by system and step, clamped into the unit cube) and rebuilds its tables
+  and lists;
 - requests wait in arrival order; whenever one of `n_slots` streams is free,
   the waiting requests (at most one per system, since a system's steps are
   sequential) are packed into one batched build (fmmds_batch_*) and launched
@@ -89,16 +90,14 @@ class Server:
         self.reset()
 
     def _prewarm(self):
-        """One-time initialization (random-number kernels on every stream, the
-        batched path) before any request is timed."""
+        """One-time initialization (the displacement and batched-build code on
+        every stream) before any request is timed."""
         torch, F = self.torch, self.F
         pts = np.ascontiguousarray(I.uniform_points(1, 300))
         for slot in self.slots:
-            g = torch.Generator(device="cuda")
-            g.manual_seed(1)
             with torch.cuda.stream(slot.stream):
-                torch.randn((16, 3), generator=g, device="cuda")
                 x = torch.from_numpy(pts).cuda()
+                F.displace([(x, 1, 0)], 0.0, stream=slot.stream)
             b = F.Batch(np.asarray([0, 100, 300], np.uint64), np.asarray([2, 3], np.uint8),
                         stream=slot.stream)
             b.launch(x)
@@ -122,14 +121,17 @@ class Server:
         self.host_ms = {"create": [], "stage": [], "launch": [], "wait": [], "release": []}
         torch.cuda.synchronize()
 
-    def _displace(self, s: int, stream):
-        torch = self.torch
-        g = torch.Generator(device="cuda")
-        g.manual_seed(I.displacement_seed(self.seed, s, self.step[s]))
-        with torch.cuda.stream(stream):
-            noise = torch.randn(self.x[s].shape, generator=g, device="cuda")
-            self.x[s].add_(noise, alpha=self.sigma).clamp_(0.0, ONE_MINUS_ULP)
-        self.step[s] += 1
+    def _step(self, reqs, off, out, stream):
+        """Advance each request's system by one displacement step on the GPU
+        (one fmmds_displace for the whole batch) and assemble the batch input
+        `out` in the same pass."""
+        items = []
+        for i, r in enumerate(reqs):
+            r.step = self.step[r.system]
+            items.append((self.x[r.system], I.displacement_seed(self.seed, r.system, r.step),
+                          int(off[i])))
+            self.step[r.system] += 1
+        self.F.displace(items, self.sigma, out=out, stream=stream)
 
     def _release(self, lid):
         e = self.live[lid]
@@ -165,16 +167,18 @@ class Server:
         b = F.Batch(off, lev, stream=slot.stream)
         self.host_ms["create"].append((time.perf_counter() - tc) * 1e3)
         tc = time.perf_counter()
-        with torch.cuda.stream(slot.stream):
-            slot.xbuf = torch.empty((int(off[-1]), 3), dtype=torch.float32, device="cuda")
-        for i, r in enumerate(reqs):
-            r.step = self.step[r.system]
-            self._displace(r.system, slot.stream)
+        total = int(off[-1])
+        if slot.xbuf is None or slot.xbuf.shape[0] < total:
+            # the slot's input buffer: reused once the slot's previous batch is done
             with torch.cuda.stream(slot.stream):
-                slot.xbuf[int(off[i]):int(off[i + 1])].copy_(self.x[r.system])
-                if r.rid in self.keep_inputs:
-                    self.kept_inputs[r.rid] = self.x[r.system].clone()
+                slot.xbuf = torch.empty((max(total, self.max_batch_points), 3),
+                                        dtype=torch.float32, device="cuda")
+        self._step(reqs, off, slot.xbuf, slot.stream)
+        for r in reqs:
             r.launched = now
+            if r.rid in self.keep_inputs:
+                with torch.cuda.stream(slot.stream):
+                    self.kept_inputs[r.rid] = self.x[r.system].clone()
         self.host_ms["stage"].append((time.perf_counter() - tc) * 1e3)
         tc = time.perf_counter()
         b.launch(slot.xbuf)
@@ -203,7 +207,7 @@ class Server:
                 tc = time.perf_counter()
                 self._release(old[0])
                 self.host_ms["release"].append((time.perf_counter() - tc) * 1e3)
-        slot.batch, slot.event, slot.reqs, slot.xbuf = None, None, [], None
+        slot.batch, slot.event, slot.reqs = None, None, []
 
     def tree_of(self, rid: int):
         """The tree a request produced, while it is still resident."""
@@ -303,30 +307,28 @@ class Server:
         self.resident = 0
 
 
-def run_sequential(systems, levels, arrivals, picks, *, sigma=1e-3, seed=8):
+def run_sequential(systems, levels, arrivals, picks, *, sigma=1e-3, seed=8, final=None):
     """Baseline: the same trace served one request at a time with fmmds_build
-    on one stream. Returns the list of Requests."""
+    on one stream. Returns the list of Requests; when `final` is a list, the
+    systems' final coordinates (host arrays) are appended to it."""
     import torch
     import paper_1301_1704_amd as F
     x = [torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda() for p in systems]
     step = [0] * len(x)
     latest = [None] * len(x)
     reqs = [Request(i, int(s), float(a)) for i, (a, s) in enumerate(zip(arrivals, picks))]
-    g = torch.Generator(device="cuda")  # one-time initialization, untimed
-    g.manual_seed(1)
-    torch.randn((16, 3), generator=g, device="cuda")
+    F.displace([(x[0], 1, 0)], 0.0)  # one-time initialization, untimed
     F.build(torch.from_numpy(I.uniform_points(1, 300)).cuda(), None, max_level=3).free()
+    torch.cuda.synchronize()
+    x[0].copy_(torch.from_numpy(np.ascontiguousarray(systems[0], dtype=np.float32)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in reqs:
         while time.perf_counter() - t0 < r.arrival:
             pass
         r.launched = time.perf_counter() - t0
-        g = torch.Generator(device="cuda")
-        g.manual_seed(I.displacement_seed(seed, r.system, step[r.system]))
         r.step = step[r.system]
-        noise = torch.randn(x[r.system].shape, generator=g, device="cuda")
-        x[r.system].add_(noise, alpha=sigma).clamp_(0.0, ONE_MINUS_ULP)
+        F.displace([(x[r.system], I.displacement_seed(seed, r.system, r.step), 0)], sigma)
         step[r.system] += 1
         t = F.build(x[r.system], None, max_level=int(levels[r.system]), key_bits=64)
         torch.cuda.synchronize()
@@ -337,6 +339,8 @@ def run_sequential(systems, levels, arrivals, picks, *, sigma=1e-3, seed=8):
     for t in latest:
         if t is not None:
             t.free()
+    if final is not None:
+        final.extend(v.cpu().numpy() for v in x)
     return reqs
 
 

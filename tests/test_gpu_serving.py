@@ -75,10 +75,60 @@ def test_mix_equals_alone(F):
     srv.close()
 
 
+def displace_ref(x, seed, sigma):
+    """fmmds_displace's definition in FP64: coordinate c = 3i + d moves by
+    sigma * sqrt(-2 ln u1) cos(2 pi u2), u1 = ((h >> 40) + 1) 2^-24,
+    u2 = ((h >> 16) & 0xFFFFFF) 2^-24, h = output c of splitmix64 stream
+    `seed`; then clamped into [0, 1 - 2^-24]."""
+    n = x.shape[0]
+    h = I.splitmix64(seed, 3 * n)
+    u1 = ((h >> np.uint64(40)) + np.uint64(1)).astype(np.float64) * 2.0 ** -24
+    u2 = ((h >> np.uint64(16)) & np.uint64(0xFFFFFF)).astype(np.float64) * 2.0 ** -24
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    v = x.astype(np.float64).reshape(-1) + sigma * z
+    return np.clip(v, 0.0, 1.0 - 2.0 ** -24).reshape(n, 3)
+
+
+# FP32 evaluation (logf, cosf, one rounding of x + sigma z) against FP64:
+# well under one unit in the last place of a coordinate in [0, 1).
+DISPLACE_TOL = 2.0 ** -23
+
+
+def test_displace_matches_definition_and_is_batch_independent(F):
+    import torch
+    sizes = [1, 63, 64, 1000, 4097] + [7 + 13 * k for k in range(35)]  # 40 sets: two launches
+    xs = [I.uniform_points(100 + k, n) for k, n in enumerate(sizes)]
+    seeds = [I.displacement_seed(8, k, 3) for k in range(len(sizes))]
+    sigma = 1e-3
+    ref = [displace_ref(x, s, sigma) for x, s in zip(xs, seeds)]
+    # the reference itself: zero-mean, sigma-wide steps
+    d = np.concatenate([(r - x).reshape(-1) for r, x in zip(ref, xs)])
+    inner = np.abs(d) < 0.5  # clamped coordinates excluded
+    assert abs(d[inner].mean()) < 5e-5 and abs(d[inner].std() / sigma - 1) < 0.05
+    # all systems in one call, gathered into one batch input
+    dev = [torch.from_numpy(x).cuda() for x in xs]
+    first = np.concatenate([[0], np.cumsum(sizes)])
+    out = torch.full((int(first[-1]), 3), -1.0, device="cuda")
+    F.displace([(x, s, int(f)) for x, s, f in zip(dev, seeds, first)], sigma, out=out)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in dev]
+    o = out.cpu().numpy()
+    for k in range(len(sizes)):
+        assert np.max(np.abs(got[k].astype(np.float64) - ref[k])) <= DISPLACE_TOL, k
+        assert np.array_equal(o[first[k]:first[k + 1]], got[k])
+        assert got[k].min() >= 0.0 and got[k].max() <= np.float32(1.0 - 2.0 ** -24)
+    # each system alone gives the same bits
+    for k in (0, 4, 39):
+        x = torch.from_numpy(xs[k]).cuda()
+        F.displace([(x, seeds[k], 0)], sigma)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), got[k])
+
+
 def test_displacement_sequence_matches_sequential_baseline(F):
     """The server and the one-at-a-time baseline apply the same seeded
     displacements in the same per-system order: the final coordinates agree
-    bit for bit."""
+    bit for bit, and with the FP64 definition replayed on the host."""
     import torch
     from paper_1301_1704_amd import serving as S
     systems, levels = _systems(6, 5)
@@ -88,18 +138,20 @@ def test_displacement_sequence_matches_sequential_baseline(F):
     torch.cuda.synchronize()
     final_server = [x.cpu().numpy() for x in srv.x]
     srv.close()
-    reqs = S.run_sequential(systems, levels, arr, pick)
-    # replay the displacements on the host side through torch again
-    x = [torch.from_numpy(np.ascontiguousarray(p)).cuda() for p in systems]
-    steps = [0] * len(x)
+    seq = []
+    reqs = S.run_sequential(systems, levels, arr, pick, final=seq)
+    assert all(r.done >= r.arrival for r in reqs)
+    steps = [0] * len(systems)
+    x = [np.ascontiguousarray(p) for p in systems]
     for r in reqs:
-        g = torch.Generator(device="cuda")
-        g.manual_seed(I.displacement_seed(8, r.system, steps[r.system]))
-        noise = torch.randn(x[r.system].shape, generator=g, device="cuda")
-        x[r.system].add_(noise, alpha=1e-3).clamp_(0.0, S.ONE_MINUS_ULP)
+        x[r.system] = displace_ref(x[r.system], I.displacement_seed(8, r.system,
+                                                                    steps[r.system]), 1e-3)
         steps[r.system] += 1
-    for a, b in zip(final_server, x):
-        assert np.array_equal(a, b.cpu().numpy())
+    for k, a in enumerate(final_server):
+        assert np.max(np.abs(a.astype(np.float64) - x[k])) <= len(reqs) * DISPLACE_TOL
+    assert len(seq) == len(final_server)
+    for a, b in zip(final_server, seq):
+        assert np.array_equal(a, b)
 
 
 def test_admission_waits_for_memory_and_rejects_oversize(F):

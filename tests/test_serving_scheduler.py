@@ -102,6 +102,10 @@ class _Lib:
     def batch_footprint(off, lev):
         return int(off[-1]) * 10
 
+    @staticmethod
+    def displace(items, sigma, out=None, stream=None):
+        pass
+
 
 SIZES = (100, 200, 300, 400, 500, 600, 700, 800)
 
@@ -116,7 +120,6 @@ def _server(budget, slots=4):
     srv.max_batch_points, srv.max_batch_sets = 1 << 24, 64
     srv.slots = [S._Slot(stream=None) for _ in range(slots)]
     srv.budget, srv.keep_inputs, srv.stall_seconds = budget, set(), 5.0
-    srv._displace = lambda s, stream: srv.step.__setitem__(s, srv.step[s] + 1)
     srv.reset()
     return srv
 
