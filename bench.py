@@ -69,10 +69,7 @@ def counter_traffic(workload_name: str, kernel_class: str):
 
 
 KERNEL_CLASS = [  # rocprofv3 kernel name (namespace and arguments stripped) -> class
-    ("k_lists<unsigned long, unsigned int, 1>", "list_fill"),
-    ("k_lists<unsigned int, unsigned int, 1>", "list_fill"),
-    ("k_lists<unsigned long, unsigned int, 0>", "list_count"),
-    ("k_lists<unsigned int, unsigned int, 0>", "list_count"),
+    ("k_list_fill", "list_fill"), ("k_list_count", "list_count"),
     ("k_scan_counts2", "scan_counts"), ("k_sort_pass", "sort_pass"), ("k_keygen", "keygen"),
     ("k_digit_offsets", "digit_offsets"), ("k_zero", "zero"), ("k_leaf", "leaf"),
     ("k_level", "level"), ("k_max_occupancy", "max_occupancy")]
@@ -143,6 +140,32 @@ def counter_summary(fetch_csv: str, write_csv: str, out: str, workload_name: str
     lines += ["", "Averages over every dispatch of the runs (all builds have the same shape). "
               "Lines read by bench.py (`sha` = the kernel source the counters were taken "
               "with; bench.py reports no traffic once it differs):", "", "```"] + data + ["```"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def kernel_stats_summary(stats_csv: str, out: str, workload_name: str):
+    """Writes the per-kernel timing summary (profiles/) from the
+    run_kernel_stats.csv of a rocprofv3 --kernel-trace --stats run of this
+    script."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+           "-d <dir> -o run -- python3 <repo>/bench.py --workload " + workload_name +
+           " --no-cpu-baseline --no-batch --no-serving")
+    lines = [f"# Kernel times (rocprofv3 --kernel-trace --stats), workload `{workload_name}`", "",
+             "```", cmd, f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
+             f"{os.path.relpath(out, ROOT)} --workload {workload_name}", "```", "",
+             "Every dispatch of the run (calibration, warm-up and timed builds alike; all have the "
+             "same shape). Averages are per dispatch, over every level of both point sets.", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | share |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        short = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f}% |")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -285,7 +308,12 @@ def main():
                     help="skip the per-kernel event timing (no roofline object)")
     ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--kernel-stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write the kernel timing summary from a rocprofv3 --stats run and exit")
     args = ap.parse_args()
+    if args.kernel_stats_summary:
+        kernel_stats_summary(*args.kernel_stats_summary, args.workload)
+        return
     if args.counter_summary:
         counter_summary(*args.counter_summary, args.workload)
         return
