@@ -130,18 +130,14 @@ __global__ __launch_bounds__(256) void k_list_count(ListLevelArgs a, uint32_t* _
   // E2 of one octant <= 27.
   const uint32_t ta = __shfl(half_incl_scan(wa), 31, 32);
   const uint32_t tb = __shfl(half_incl_scan(wb), 31, 32);
-  uint32_t k = 0;
-  uint32_t qm = rmask;
-#pragma unroll 1
-  while (qm) {
-    const uint32_t q = __builtin_ctz(qm);
-    qm &= qm - 1;
-    if (j == 0) {
-      const uint32_t n2 = octant_field(ta, tb, q);
-      cnt2[rfirst + k] = n2;
-      cnt4[rfirst + k] = (ta & 0xFFu) - n2;
-    }
-    ++k;
+  // Lane j writes the counts of receiver child j (octant: the j-th set bit
+  // of the mask), so the children's counts leave in one store each.
+  if (j < (uint32_t)__popc(rmask)) {
+    uint32_t mm = rmask;
+    for (uint32_t t = 0; t < j; ++t) mm &= mm - 1;
+    const uint32_t n2 = octant_field(ta, tb, (uint32_t)__builtin_ctz(mm));
+    cnt2[rfirst + j] = n2;
+    cnt4[rfirst + j] = (ta & 0xFFu) - n2;
   }
 }
 
@@ -307,6 +303,8 @@ void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
 // in one single pass. off[n] = total; the totals also go to total[0..1], and
 // the overflow flag is set if a total does not fit 32-bit offsets. Wave 0
 // chains the E2 sums across tiles, wave 1 the E4 sums, at the same time.
+// Each thread owns 16 consecutive boxes, read and written with 16-byte
+// accesses (both count arrays and both offset arrays start 16-byte aligned).
 // ---------------------------------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kCompBlock * kScanItems;  // 4096 boxes
@@ -328,12 +326,26 @@ __global__ __launch_bounds__(kCompBlock) void k_scan_counts2(
   if ((uint64_t)tile * kScanTile >= n) return;  // whole block: surplus tile
   const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)tid * kScanItems;
   uint32_t v2[kScanItems], v4[kScanItems];
+  const bool full = base + kScanItems <= n;  // 16-byte loads and stores
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const uint4 a2 = ((const uint4*)(cnt2 + base))[q];
+      const uint4 a4 = ((const uint4*)(cnt4 + base))[q];
+      v2[4 * q] = a2.x, v2[4 * q + 1] = a2.y, v2[4 * q + 2] = a2.z, v2[4 * q + 3] = a2.w;
+      v4[4 * q] = a4.x, v4[4 * q + 1] = a4.y, v4[4 * q + 2] = a4.z, v4[4 * q + 3] = a4.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const bool ok = base + i < n;
+      v2[i] = ok ? cnt2[base + i] : 0;
+      v4[i] = ok ? cnt4[base + i] : 0;
+    }
+  }
   uint32_t sum2 = 0, sum4 = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const bool ok = base + i < n;
-    v2[i] = ok ? cnt2[base + i] : 0;
-    v4[i] = ok ? cnt4[base + i] : 0;
     sum2 += v2[i];
     sum4 += v4[i];
   }
@@ -363,18 +375,37 @@ __global__ __launch_bounds__(kCompBlock) void k_scan_counts2(
   uint64_t pre2 = s_excl[0] + wpre2 + inc2 - sum2;
   uint64_t pre4 = s_excl[1] + wpre4 + inc4 - sum4;
   bool ovf = false;
+  if (full) {
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) {
-      off2[base + i] = (uint32_t)pre2;
-      off4[base + i] = (uint32_t)pre4;
-      pre2 += v2[i];
-      pre4 += v4[i];
-      if (base + i + 1 == n) {
-        off2[n] = (uint32_t)pre2;
-        off4[n] = (uint32_t)pre4;
-        *total2 = pre2;
-        *total4 = pre4;
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      uint4 o2, o4;
+      o2.x = (uint32_t)pre2, pre2 += v2[4 * q], o4.x = (uint32_t)pre4, pre4 += v4[4 * q];
+      o2.y = (uint32_t)pre2, pre2 += v2[4 * q + 1], o4.y = (uint32_t)pre4, pre4 += v4[4 * q + 1];
+      o2.z = (uint32_t)pre2, pre2 += v2[4 * q + 2], o4.z = (uint32_t)pre4, pre4 += v4[4 * q + 2];
+      o2.w = (uint32_t)pre2, pre2 += v2[4 * q + 3], o4.w = (uint32_t)pre4, pre4 += v4[4 * q + 3];
+      ((uint4*)(off2 + base))[q] = o2;
+      ((uint4*)(off4 + base))[q] = o4;
+    }
+    if (base + kScanItems == n) {
+      off2[n] = (uint32_t)pre2;
+      off4[n] = (uint32_t)pre4;
+      *total2 = pre2;
+      *total4 = pre4;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < n) {
+        off2[base + i] = (uint32_t)pre2;
+        off4[base + i] = (uint32_t)pre4;
+        pre2 += v2[i];
+        pre4 += v4[i];
+        if (base + i + 1 == n) {
+          off2[n] = (uint32_t)pre2;
+          off4[n] = (uint32_t)pre4;
+          *total2 = pre2;
+          *total4 = pre4;
+        }
       }
     }
   }

@@ -604,7 +604,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     la.words = (uint64_t*)(lws + ltick_b);
     la.n_words = lwords;
     P.run(K_ZERO, (double)lws_b, [&] { launch_zero(lws, lws_b, st); });
-    uint32_t* cnt = temps.get<uint32_t>(2 * std::max<size_t>(lmax, 1));
+    // E2 counts, then E4 counts from a 16-byte aligned start (vector loads)
+    uint32_t* cnt = temps.get<uint32_t>(2 * round_up(std::max<size_t>(lmax, 1), 4));
     for (uint32_t l = 2; l <= D; ++l) {
       const uint32_t nr = nb[rs][l];
       ListLevelArgs a{};
@@ -629,7 +630,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
       const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
-      P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + nr, st); });
+      P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
       LB.off[0] = impl->outs.get<uint32_t>((size_t)nr + 1);
       LB.off[1] = impl->outs.get<uint32_t>((size_t)nr + 1);
       {
@@ -637,7 +638,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         uint64_t* st4 = la.take_words(scan_tiles(nr));
         uint32_t* tk = la.take_ticket();
         P.run(K_SCAN, (double)nr * 16 + 8, [&] {
-          launch_scan_counts2(cnt, cnt + nr, nr, LB.off[0], LB.off[1], &meta->list_total[0][l],
+          launch_scan_counts2(cnt, cnt + round_up(nr, 4), nr, LB.off[0], LB.off[1], &meta->list_total[0][l],
                               &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st);
         });
       }
@@ -876,7 +877,7 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
     a.set_level = B.d_lev;
     a.key_bits_up = B.setbits + 3 * (l - 1);
     uint32_t* c2 = B.cnt;
-    uint32_t* c4 = B.cnt + B.cap[l];
+    uint32_t* c4 = B.cnt + round_up(B.cap[l], 4);
     P.run(K_COUNT, 0.0, [&] { launch_list_count(true, a, c2, c4, st); });
     {
       uint64_t* st2 = sa.take_words(scan_tiles(B.cap[l]));
@@ -1043,7 +1044,7 @@ void batch_layout(BatchImpl& B, Carve& M) {
       }
     }
   }
-  B.cnt = M.get<uint32_t>(2 * (size_t)std::max<uint32_t>(cmax, 1));
+  B.cnt = M.get<uint32_t>(2 * round_up(std::max<uint32_t>(cmax, 1), 4));
   // metadata block and the zeroed workspace around it
   B.first_at = round_up(sizeof(DevMeta), 256);
   B.base_at = round_up(B.first_at + (size_t)(L + 1) * (n_sets + 1) * 4, 256);

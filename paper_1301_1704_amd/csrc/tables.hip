@@ -145,6 +145,19 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
   const uint64_t tbase = (uint64_t)tile * kCompTile;
   if (tbase >= n_in) return;  // whole block: no valid element in this tile
 
+  // Loads first, from indices clamped into [0, n_in) so that they are
+  // unconditional and all in flight at once (results past n_in are
+  // discarded); every load precedes every store, since on this GPU a wait
+  // for a load also waits for all earlier stores.
+  uint64_t kv[kCompItems], kp[kCompItems];
+  uint32_t bfirst[kCompItems];
+#pragma unroll
+  for (int i = 0; i < kCompItems; ++i) {
+    const uint64_t jc = min<uint64_t>(tbase + (uint64_t)i * kCompBlock + tid, n_in - 1);
+    kv[i] = (uint64_t)kin[jc];
+    kp[i] = (uint64_t)kin[jc > 0 ? jc - 1 : 0];
+    bfirst[i] = bin[jc];
+  }
   uint64_t pkey[kCompItems];
   uint32_t incl[kCompItems];
   uint32_t cmask[kCompItems];  // child octants of the parent a flagged box starts
@@ -154,15 +167,9 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;
     const bool valid = j < n_in;
-    uint64_t pk = 0, pp = 0;
-    uint32_t oct = 8;
-    if (valid) {
-      const uint64_t k = (uint64_t)kin[j];
-      pk = k >> 3;
-      oct = (uint32_t)(k & 7u);
-      if (j > 0) pp = (uint64_t)kin[j - 1] >> 3;
-    }
-    const bool f = valid && (j == 0 || pk != pp);
+    const uint64_t pk = kv[i] >> 3;
+    const uint32_t oct = valid ? (uint32_t)(kv[i] & 7u) : 8u;
+    const bool f = valid && (j == 0 || pk != (kp[i] >> 3));
     const uint64_t ball = __ballot(f);
     incl[i] = mbcnt(ball) + (f ? 1u : 0u);
     flags |= (f ? 1u : 0u) << i;
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
     pout[j] = rank;
     if ((flags >> i) & 1u) {
       kout[rank] = (KeyT)pkey[i];
-      bout[rank] = bin[j];
+      bout[rank] = bfirst[i];
       cout[rank] = (uint32_t)j;
       mout[rank] = (uint8_t)cmask[i];
     }
