@@ -54,6 +54,15 @@ __device__ __forceinline__ int axis_delta(A sk, A pk, A axis_mask, A axis_low) {
   return d == 0 ? 0 : (d == axis_low ? 1 : -1);
 }
 
+// Blocks are dispatched to the 8 XCDs (each with its own L2) round-robin:
+// block b runs on XCD b % 8. Renumbering so that each XCD takes one
+// contiguous range of work keeps each XCD's reads and writes in one region
+// of memory. A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, q = n >> 3, r = n & 7u;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // Inclusive scan within each 32-lane half of the wave.
 __device__ __forceinline__ uint32_t half_incl_scan(uint32_t v) {
   const uint32_t j = lane_id() & 31u;
@@ -78,7 +87,7 @@ __global__ __launch_bounds__(256) void k_list_count(ListLevelArgs a, uint32_t* _
   const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
   const uint32_t j = threadIdx.x & 31u, h = threadIdx.x >> 5;
-  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  const uint64_t p = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 8 + h;
   const uint32_t n_up = a.n_recv_up_dev ? *a.n_recv_up_dev : a.n_recv_up;
   if (p >= n_up) return;  // whole half-wave
   // upbase: batch rank of the set's first box at level - 1 (parent-level E2
@@ -151,9 +160,10 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
   const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
   const uint32_t lane = threadIdx.x & 63u, j = lane & 31u, h = threadIdx.x >> 5;
-  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  const uint64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint64_t p = blk * 8 + h;
   const uint32_t n_up = a.n_recv_up_dev ? *a.n_recv_up_dev : a.n_recv_up;
-  if ((uint64_t)blockIdx.x * 8 + (h & ~1u) >= n_up) return;  // whole wave: both parents absent
+  if (blk * 8 + (h & ~1u) >= n_up) return;  // whole wave: both parents absent
   const bool live = p < n_up;
   // Setup, one half-wave per parent p (lane j: the j-th entry s of E2(p)).
   // upbase: batch rank of the set's first box at level - 1 (parent-level E2
