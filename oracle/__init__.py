@@ -64,6 +64,8 @@ def lib():
         L.oref_list_sizes.argtypes = [vp, i32, u32, C.POINTER(u32), C.POINTER(u64)]
         L.oref_list.argtypes = [vp, i32, u32, vp, vp]
         L.oref_box_list.argtypes = [vp, i32, u32, u32, vp]
+        L.oref_partition.argtypes = [vp, u32, u32, vp]
+        L.oref_box_types.argtypes = [vp, u32, vp, u32, vp]
         _lib = L
     return _lib
 
@@ -176,3 +178,23 @@ class OracleTree:
         if n < 0:
             raise OracleError(-n, "oref_box_list")
         return buf[:n].copy()
+
+    def partition(self, l_par: int, n_ranks: int) -> np.ndarray:
+        """Rank of every Morton index at level l_par (Section 3.2)."""
+        out = np.empty(1 << (3 * l_par), dtype=np.uint32)
+        st = lib().oref_partition(self._h, l_par, n_ranks, _ptr(out))
+        if st != OK:
+            raise OracleError(st, "oref_partition")
+        return out
+
+    def box_types(self, l_par: int, owner: np.ndarray, rank: int) -> list:
+        """Source box types of `rank` per level 2..depth (list of uint8
+        arrays; index 0 is level 2): DOMESTIC 0, EXPORT 1, IMPORT 2, ROOT 3,
+        OTHER 4 (Section 3.1, Algorithm 6)."""
+        ow = np.ascontiguousarray(owner, dtype=np.uint32)
+        sizes = [self.n_boxes(SRC, l) for l in range(2, self.depth + 1)]
+        out = np.empty(sum(sizes), dtype=np.uint8)
+        st = lib().oref_box_types(self._h, l_par, _ptr(ow), rank, _ptr(out))
+        if st != OK:
+            raise OracleError(st, "oref_box_types")
+        return np.split(out, np.cumsum(sizes)[:-1])

@@ -427,4 +427,111 @@ int oref_box_list(const oref_tree* t, int kind, uint32_t level, uint32_t recv_bo
   return (int)tmp.size();
 }
 
+
+// ---------------------------------------------------------------------------
+// Simulated partition and source box types (Section 3).
+// ---------------------------------------------------------------------------
+
+// Section 3.2: the boxes of the partition level l_par are given to the ranks
+// in consecutive Morton ranges balanced by receiver points. Written out: the
+// nonempty receiver box b at l_par whose first point (in Morton order) is the
+// p-th of M goes to rank min(R - 1, floor(R * p / M)); every other Morton
+// index at l_par takes the rank of the nearest nonempty receiver box before
+// it, or rank 0 if there is none.
+int oref_partition(const oref_tree* t, uint32_t l_par, uint32_t n_ranks, uint32_t* owner_out) {
+  if (!t || !owner_out || n_ranks == 0) return OREF_ERR_ARG;
+  if (l_par < 3 || l_par > t->depth || 3 * l_par > 30) return OREF_ERR_LEVEL;
+  const Level& rl = t->set(1).lv[l_par];
+  const uint64_t M = t->set(1).sorted_key.size();
+  const uint64_t n_idx = 1ull << (3 * l_par);
+  size_t b = 0;  // next nonempty receiver box
+  uint32_t cur = 0;
+  for (uint64_t m = 0; m < n_idx; ++m) {
+    if (b < rl.key.size() && rl.key[b] == m) {
+      const uint64_t p = rl.begin[b];
+      cur = (uint32_t)std::min<uint64_t>(n_ranks - 1, (uint64_t)n_ranks * p / M);
+      ++b;
+    }
+    owner_out[m] = cur;
+  }
+  return OREF_OK;
+}
+
+// Source box types for rank J (Section 3.1, Algorithm 6), levels 2..depth
+// concatenated (level l's n_src_l entries after those of the levels below).
+// DOMESTIC 0, EXPORT 1, IMPORT 2, ROOT 3, OTHER 4. Reading of the algorithm:
+// the critical level is l_crit = l_par - 1 (l_par >= 3); below it every box
+// is DOMESTIC. At l_crit a box whose nonempty source children (at l_par) are
+// all on other ranks is IMPORT, one with children on J and elsewhere is ROOT;
+// one with all children on J is EXPORT if some receiver box r at l_crit that
+// has k in its M2L list E4(r) has a nonempty receiver child on another rank,
+// else DOMESTIC. From l_par down, the owner of a box is the owner of its
+// ancestor at l_par: a box on J is EXPORT if some receiver box on another rank
+// has it in its E4 list, else DOMESTIC; a box on another rank is IMPORT if
+// some receiver box on J has it in its E4 list, else OTHER.
+int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
+                   uint8_t* types_out) {
+  enum { DOMESTIC = 0, EXPORT = 1, IMPORT = 2, ROOT = 3, OTHER = 4 };
+  if (!t || !owner || !types_out) return OREF_ERR_ARG;
+  if (l_par < 3 || l_par > t->depth || 3 * l_par > 30) return OREF_ERR_LEVEL;
+  const uint32_t l_crit = l_par - 1;
+  const PointSet& S = t->set(0);
+  const PointSet& R = t->set(1);
+  auto own = [&](uint64_t key, uint32_t l) { return owner[key >> (3 * (l - l_par))]; };
+  std::vector<uint32_t> lst;
+  size_t at = 0;
+  for (uint32_t l = 2; l <= t->depth; ++l) {
+    const Level& sl = S.lv[l];
+    const Level& rl = R.lv[l];
+    const size_t ns = sl.key.size();
+    uint8_t* ty = types_out + at;
+    at += ns;
+    if (l < l_crit) {
+      for (size_t k = 0; k < ns; ++k) ty[k] = DOMESTIC;
+      continue;
+    }
+    Lookup look(sl, l, false);
+    std::vector<char> needed_elsewhere(ns, 0), needed_here(ns, 0);
+    if (l == l_crit) {
+      // receiver boxes at l_crit with a nonempty receiver child on another rank
+      const Level& rc = R.lv[l_par];
+      for (size_t r = 0; r < rl.key.size(); ++r) {
+        bool remote = false;
+        for (size_t c = 0; c < rc.key.size(); ++c)
+          if ((rc.key[c] >> 3) == rl.key[r] && own(rc.key[c], l_par) != rank) remote = true;
+        if (!remote) continue;
+        box_list(look, 4, rl.key[r], l, lst);
+        for (uint32_t k : lst) needed_elsewhere[k] = 1;
+      }
+      const Level& sc = S.lv[l_par];
+      for (size_t k = 0; k < ns; ++k) {
+        bool on = false, off = false;
+        for (size_t c = 0; c < sc.key.size(); ++c) {
+          if ((sc.key[c] >> 3) != sl.key[k]) continue;
+          if (own(sc.key[c], l_par) == rank) on = true;
+          else off = true;
+        }
+        if (!on) ty[k] = IMPORT;
+        else if (off) ty[k] = ROOT;
+        else ty[k] = needed_elsewhere[k] ? EXPORT : DOMESTIC;
+      }
+      continue;
+    }
+    for (size_t r = 0; r < rl.key.size(); ++r) {
+      const bool r_here = own(rl.key[r], l) == rank;
+      box_list(look, 4, rl.key[r], l, lst);
+      for (uint32_t k : lst) {
+        const bool k_here = own(sl.key[k], l) == rank;
+        if (k_here && !r_here) needed_elsewhere[k] = 1;
+        if (!k_here && r_here) needed_here[k] = 1;
+      }
+    }
+    for (size_t k = 0; k < ns; ++k) {
+      if (own(sl.key[k], l) == rank) ty[k] = needed_elsewhere[k] ? EXPORT : DOMESTIC;
+      else ty[k] = needed_here[k] ? IMPORT : OTHER;
+    }
+  }
+  return OREF_OK;
+}
+
 }  // extern "C"

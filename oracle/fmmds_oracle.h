@@ -70,6 +70,17 @@ int oref_list(const oref_tree* t, int kind, uint32_t level, uint32_t* offsets, u
 int oref_box_list(const oref_tree* t, int kind, uint32_t level, uint32_t recv_box,
                   uint32_t* entries);
 
+/* Simulated partition (Section 3.2): the rank owning every Morton index of
+ * level l_par (dense, 8^l_par entries), consecutive Morton ranges balanced
+ * by receiver points. Needs 3 <= l_par <= depth. */
+int oref_partition(const oref_tree* t, uint32_t l_par, uint32_t n_ranks, uint32_t* owner_out);
+
+/* Source box types of rank `rank` (Section 3.1, Algorithm 6) for levels
+ * 2..depth, concatenated: DOMESTIC 0, EXPORT 1, IMPORT 2, ROOT 3, OTHER 4.
+ * `owner`: 8^l_par ranks as from oref_partition. */
+int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
+                   uint8_t* types_out);
+
 #ifdef __cplusplus
 }
 #endif

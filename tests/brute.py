@@ -110,3 +110,81 @@ def max_occupancy(points, level: int) -> int:
         k = morton_by_digits(p, level)
         counts[k] = counts.get(k, 0) + 1
     return max(counts.values())
+
+
+# ------------------------------------------------------- partition, box types
+
+def partition(recv, l_par: int, n_ranks: int):
+    """Rank of every Morton index at l_par (Section 3.2 reading): a nonempty
+    receiver box whose first point is the p-th of M in Morton order goes to
+    rank min(R - 1, R * p // M); other indices take the rank of the nearest
+    nonempty box before them (0 if none). Counted from exact coordinates."""
+    counts = {}
+    for p in recv:
+        k = morton_by_digits(p, l_par)
+        counts[k] = counts.get(k, 0) + 1
+    M = len(recv)
+    owner, before, cur = [], 0, 0
+    for m in range(8 ** l_par):
+        if m in counts:
+            cur = min(n_ranks - 1, n_ranks * before // M)
+            before += counts[m]
+        owner.append(cur)
+    return owner
+
+
+def box_types(src, recv, L: int, depth: int, l_par: int, owner, rank: int):
+    """Source box types of `rank` per level 2..depth (DOMESTIC 0, EXPORT 1,
+    IMPORT 2, ROOT 3, OTHER 4), from box coordinates and pair tests."""
+    sp, st = tables(src, L, depth)
+    rp, rt = tables(recv, L, depth)
+    l_crit = l_par - 1
+
+    def own_of(c, l):  # owner of the level-l box with coordinates c
+        a = [v >> (l - l_par) for v in c]
+        key = 0
+        for m in range(l_par - 1, -1, -1):  # digits from the coarsest level
+            key = (key << 3) | (((a[0] >> m) & 1) | (((a[1] >> m) & 1) << 1) |
+                                (((a[2] >> m) & 1) << 2))
+        return owner[key]
+
+    def m2l(r, k):  # k in E4(r)
+        cheb = max(abs(r[i] - k[i]) for i in range(3))
+        pcheb = max(abs((r[i] >> 1) - (k[i] >> 1)) for i in range(3))
+        return cheb >= 2 and pcheb <= 1
+
+    out = []
+    for l in range(2, depth + 1):
+        sc = box_coords(src, sp, st, l)
+        rc = box_coords(recv, rp, rt, l)
+        if l < l_crit:
+            out.append([0] * len(sc))
+            continue
+        types = []
+        if l == l_crit:
+            sch = box_coords(src, sp, st, l_par)
+            rch = box_coords(recv, rp, rt, l_par)
+            remote = [any(tuple(v >> 1 for v in c) == tuple(r) and own_of(c, l_par) != rank
+                          for c in rch) for r in rc]
+            for k in sc:
+                kids = [c for c in sch if tuple(v >> 1 for v in c) == tuple(k)]
+                on = any(own_of(c, l_par) == rank for c in kids)
+                off = any(own_of(c, l_par) != rank for c in kids)
+                if not on:
+                    types.append(2)
+                elif off:
+                    types.append(3)
+                else:
+                    need = any(remote[i] and m2l(r, k) for i, r in enumerate(rc))
+                    types.append(1 if need else 0)
+        else:
+            for k in sc:
+                here = own_of(k, l) == rank
+                if here:
+                    need = any(own_of(r, l) != rank and m2l(r, k) for r in rc)
+                    types.append(1 if need else 0)
+                else:
+                    need = any(own_of(r, l) == rank and m2l(r, k) for r in rc)
+                    types.append(2 if need else 4)
+        out.append(types)
+    return out

@@ -99,6 +99,38 @@ def test_degenerate_inputs(F, oracle_lib):
     _run(F, oracle_lib, pts, pts[::-1].copy(), L=8)[0].free()
 
 
+def test_deepest_levels(F, oracle_lib):
+    """The key-width limits: max level 21 with 64-bit keys (63 key bits) and
+    max level 10 with 32-bit keys (30 bits, the packed sort at its limit)."""
+    src = I.sphere_cluster_points(61, 60, 20000)
+    recv = I.sphere_cluster_points(62, 60, 15000)
+    _run(F, oracle_lib, src, recv, L=21, kb=64)[0].free()
+    _run(F, oracle_lib, src, recv, L=10, kb=32)[0].free()
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 6])
+def test_full_grid_closed_forms(F, oracle_lib, L):
+    """One point per box at level L: every box of every level is nonempty and
+    the list totals equal the closed forms of the E2 / E4 definitions; at
+    L <= 5 the whole output is also compared with the oracle."""
+    import golden_io
+    forms = {r[0]: (r[1], r[2]) for r in golden_io.read_table("closed_forms.txt")}
+    pts = I.full_grid_points(L)
+    if L <= 5:
+        g, _ = _run(F, oracle_lib, pts, None, L=L)
+    else:
+        import torch
+        _say(f"case full grid L={L}")
+        g = F.build(parity.to_gpu(pts), None, max_level=L, key_bits=64)
+        torch.cuda.synchronize()
+    for l in range(L + 1):
+        assert g.n_boxes(0, l) == 8 ** l
+    e2 = g.neighbors(L)[3]
+    e4 = g.interactions(L)[3]
+    assert (e2, e4) == forms[L]
+    g.free()
+
+
 def test_key_width_does_not_change_other_outputs(F):
     import torch
     src = parity.to_gpu(I.uniform_points(51, 30000))

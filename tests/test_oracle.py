@@ -279,3 +279,87 @@ def test_invariants_and_symmetry_shared(oracle_lib):
                 pairs.update((r, int(s)) for s in row)
             assert pairs == {(s, r) for (r, s) in pairs}, (kind, l)
             assert np.diff(off.astype(np.int64)).max() <= (27 if kind == 2 else 189)
+
+
+# ------------------------------------------- simulated partition, box types
+
+TYPE_CASES = [
+    ("uniform", I.uniform_points(71, 150), None, 4),
+    ("separate", I.uniform_points(72, 120), I.sphere_cluster_points(73, 74, 140), 4),
+    ("clustered", I.sphere_cluster_points(75, 76, 160), None, 5),
+]
+
+
+@pytest.mark.parametrize("name,src,recv,L", TYPE_CASES, ids=[c[0] for c in TYPE_CASES])
+@pytest.mark.parametrize("n_ranks", [1, 2, 3, 5])
+def test_partition_and_box_types_by_brute_force(oracle_lib, name, src, recv, L, n_ranks):
+    """Section 3.2 partition and Section 3.1 box types against pair
+    enumeration on exact box coordinates, for every rank."""
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
+    sp = [tuple(p) for p in src]
+    rp = sp if recv is None else [tuple(p) for p in recv]
+    for l_par in range(3, L + 1):
+        owner = t.partition(l_par, n_ranks)
+        assert owner.tolist() == brute.partition(rp, l_par, n_ranks), l_par
+        for rank in range(n_ranks):
+            exp = brute.box_types(sp, rp, L, L, l_par, owner.tolist(), rank)
+            got = t.box_types(l_par, owner, rank)
+            assert [g.tolist() for g in got] == exp, (l_par, rank)
+
+
+def test_single_rank_is_all_domestic(oracle_lib):
+    p = I.sphere_cluster_points(77, 78, 3000)
+    t = oracle_lib.OracleTree(p, key_bits=64, max_level=6)
+    for l_par in (3, 4, 6):
+        owner = t.partition(l_par, 1)
+        assert not owner.any()
+        for ty in t.box_types(l_par, owner, 0):
+            assert not ty.any()
+
+
+def test_box_types_full_grid_closed_form(oracle_lib):
+    """Counts per type on the full grid split by the plane z = 1/2 (the
+    derivation is in the fixture)."""
+    rows = golden_io.read_table("box_types_full_grid.txt")
+    t = oracle_lib.OracleTree(I.full_grid_points(5), key_bits=64, max_level=5)
+    owner = t.partition(3, 2)
+    assert owner.tolist() == [0] * 256 + [1] * 256
+    for rank in (0, 1):
+        types = t.box_types(3, owner, rank)
+        for row in rows:
+            l, counts = row[0], row[1:]
+            assert np.bincount(types[l - 2], minlength=5).tolist() == counts, (rank, l)
+
+
+def test_root_boxes_where_the_split_cuts_a_critical_box(oracle_lib):
+    """Three ranks over the 512 equal level-3 boxes of the full grid: the
+    splits at Morton indices 171 and 342 fall inside the level-2 boxes 21 and
+    42, which are the only ROOT boxes (Algorithm 6: a critical-level box with
+    children on this rank and on another)."""
+    t = oracle_lib.OracleTree(I.full_grid_points(4), key_bits=64, max_level=4)
+    owner = t.partition(3, 3)
+    assert owner.tolist() == [0] * 171 + [1] * 171 + [2] * 170
+    keys2 = t.keys(0, 2)
+    for rank, roots in ((0, [21]), (1, [21, 42]), (2, [42])):
+        ty = t.box_types(3, owner, rank)
+        assert keys2[ty[0] == 3].tolist() == roots
+        for deeper in ty[1:]:
+            assert not (deeper == 3).any()
+
+
+def test_box_types_exchange_symmetry_shared(oracle_lib):
+    """Shared sources and receivers (E4 symmetric): from l_par down, a box is
+    EXPORT on its owner exactly when it is IMPORT on some other rank."""
+    p = I.sphere_cluster_points(79, 80, 4000)
+    t = oracle_lib.OracleTree(p, key_bits=64, max_level=6)
+    R, l_par = 4, 3
+    owner = t.partition(l_par, R)
+    types = [t.box_types(l_par, owner, r) for r in range(R)]
+    for l in range(l_par, 7):
+        keys = t.keys(0, l)
+        own = owner[keys >> np.uint64(3 * (l - l_par))]
+        for i in range(keys.size):
+            on_owner = types[own[i]][l - 2][i]
+            elsewhere = [types[r][l - 2][i] for r in range(R) if r != own[i]]
+            assert on_owner in (0, 1) and all(v in (2, 4) for v in elsewhere)
+            assert (on_owner == 1) == any(v == 2 for v in elsewhere)
