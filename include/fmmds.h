@@ -223,6 +223,48 @@ typedef struct fmmds_displace_set {
 fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, float sigma,
                             float* out, void* stream);
 
+/*
+ * Simulated partition and source box types (Section 3): what one rank of a
+ * multi-node run would compute, here for any rank of a partition simulated
+ * on one GPU. Both calls read a finished tree (fmmds_build, or a batch view)
+ * and enqueue their work on `stream` (a hipStream_t; NULL = null stream),
+ * returning at once; the tree must be complete on that stream.
+ *
+ * fmmds_partition (Section 3.2: consecutive Morton ranges of the partition
+ * level l_par, balanced by receiver points): writes the rank of every Morton
+ * index of level l_par to owner[0 .. 8^l_par) (device). The nonempty
+ * receiver box whose first point is the p-th of the M receiver points (in
+ * Morton order) gets rank min(n_ranks - 1, floor(n_ranks * p / M)); every
+ * other index takes the rank of the nearest nonempty receiver box before it
+ * (rank 0 if none). Needs 3 <= l_par <= min(depth, 10) (FMMDS_ERR_LEVEL)
+ * and n_ranks >= 1 (FMMDS_ERR_ARG).
+ *
+ * fmmds_box_types (Section 3.1, Algorithm 6): the type of every nonempty
+ * source box of levels 2..depth as seen by rank `rank`, for any owner table
+ * of level l_par (such as fmmds_partition's). `types` (device) holds
+ * sum_{l=2..depth} src[l].n bytes, level l after the levels below it.
+ * With l_crit = l_par - 1: below l_crit, DOMESTIC. At l_crit: IMPORT if no
+ * nonempty source child (at l_par) is on `rank`; ROOT if some are on `rank`
+ * and some elsewhere; otherwise EXPORT if a receiver box with a nonempty
+ * receiver child elsewhere has the box in its E4 (M2L) list, else DOMESTIC.
+ * From l_par down a box is on the rank of its l_par ancestor: on `rank` it is
+ * EXPORT if a receiver box of another rank has it in its E4 list, else
+ * DOMESTIC; elsewhere it is IMPORT if a receiver box of `rank` has it in its
+ * E4 list, else OTHER. Uses a temporary device buffer of 4 bytes per source
+ * box of the largest level (library or caller allocator, as the tree's).
+ */
+enum {
+  FMMDS_BOX_DOMESTIC = 0,
+  FMMDS_BOX_EXPORT = 1,
+  FMMDS_BOX_IMPORT = 2,
+  FMMDS_BOX_ROOT = 3,
+  FMMDS_BOX_OTHER = 4
+};
+fmmds_status fmmds_partition(const fmmds_tree* t, uint32_t l_par, uint32_t n_ranks,
+                             uint32_t* owner, void* stream);
+fmmds_status fmmds_box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owner,
+                             uint32_t rank, uint8_t* types, void* stream);
+
 /* Memory the library allocates itself (opt->alloc == NULL) is cached after
  * release, per device, and reused by later builds of similar size. This call
  * synchronizes every device the cache holds memory of and returns all cached

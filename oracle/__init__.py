@@ -66,6 +66,7 @@ def lib():
         L.oref_box_list.argtypes = [vp, i32, u32, u32, vp]
         L.oref_partition.argtypes = [vp, u32, u32, vp]
         L.oref_box_types.argtypes = [vp, u32, vp, u32, vp]
+        L.oref_box_type_one.argtypes = [vp, u32, vp, u32, u32, u32]
         _lib = L
     return _lib
 
@@ -198,3 +199,12 @@ class OracleTree:
         if st != OK:
             raise OracleError(st, "oref_box_types")
         return np.split(out, np.cumsum(sizes)[:-1])
+
+    def box_type_one(self, l_par: int, owner: np.ndarray, rank: int, level: int,
+                     box: int) -> int:
+        """Type of one source box, from the definition without lists."""
+        ow = np.ascontiguousarray(owner, dtype=np.uint32)
+        v = lib().oref_box_type_one(self._h, l_par, _ptr(ow), rank, level, box)
+        if v < 0:
+            raise OracleError(-v, "oref_box_type_one")
+        return int(v)

@@ -534,4 +534,74 @@ int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, ui
   return OREF_OK;
 }
 
+// The type of one source box (level `level`, rank `box`), from the same
+// definition as oref_box_types but without lists: the receiver boxes r with
+// the box in E4(r) are found by enumerating the cells at Chebyshev distance
+// >= 2 whose parents are within 1 (the E4 condition is symmetric in r and k)
+// and looking them up among the nonempty receiver boxes. Returns the type, or
+// minus a status code.
+int oref_box_type_one(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
+                      uint32_t level, uint32_t box) {
+  enum { DOMESTIC = 0, EXPORT = 1, IMPORT = 2, ROOT = 3, OTHER = 4 };
+  if (!t || !owner) return -OREF_ERR_ARG;
+  if (l_par < 3 || l_par > t->depth || 3 * l_par > 30) return -OREF_ERR_LEVEL;
+  if (level < 2 || level > t->depth) return -OREF_ERR_LEVEL;
+  const uint32_t l_crit = l_par - 1;
+  const Level& sl = t->set(0).lv[level];
+  if (box >= sl.key.size()) return -OREF_ERR_ARG;
+  if (level < l_crit) return DOMESTIC;
+  const uint64_t kk = sl.key[box];
+  auto own = [&](uint64_t key, uint32_t l) { return owner[key >> (3 * (l - l_par))]; };
+  auto has = [](const Level& lv, uint64_t key) {
+    return std::binary_search(lv.key.begin(), lv.key.end(), key);
+  };
+  const Level& rl = t->set(1).lv[level];
+  // nonempty receiver boxes r with kk in E4(r)
+  std::vector<uint64_t> recv;
+  int64_t ck[3];
+  deinterleave(kk, level, ck);
+  const int64_t m = (int64_t)1 << level;
+  int64_t c[3];
+  for (c[2] = 2 * (floor_half(ck[2]) - 1); c[2] <= 2 * (floor_half(ck[2]) + 1) + 1; ++c[2])
+    for (c[1] = 2 * (floor_half(ck[1]) - 1); c[1] <= 2 * (floor_half(ck[1]) + 1) + 1; ++c[1])
+      for (c[0] = 2 * (floor_half(ck[0]) - 1); c[0] <= 2 * (floor_half(ck[0]) + 1) + 1; ++c[0]) {
+        bool inside = true;
+        int64_t cheb = 0, pcheb = 0;
+        for (int d = 0; d < 3; ++d) {
+          inside = inside && c[d] >= 0 && c[d] < m;
+          cheb = std::max(cheb, iabs(c[d] - ck[d]));
+          pcheb = std::max(pcheb, iabs(floor_half(c[d]) - floor_half(ck[d])));
+        }
+        if (!inside || cheb < 2 || pcheb > 1) continue;
+        const uint64_t rk = interleave((uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2], level);
+        if (has(rl, rk)) recv.push_back(rk);
+      }
+  if (level == l_crit) {
+    const Level& sc = t->set(0).lv[l_par];
+    const Level& rc = t->set(1).lv[l_par];
+    bool on = false, off = false;
+    for (uint64_t o = 0; o < 8; ++o) {
+      const uint64_t ch = (kk << 3) | o;
+      if (!has(sc, ch)) continue;
+      if (own(ch, l_par) == rank) on = true;
+      else off = true;
+    }
+    if (!on) return IMPORT;
+    if (off) return ROOT;
+    for (uint64_t rk : recv)
+      for (uint64_t o = 0; o < 8; ++o) {
+        const uint64_t ch = (rk << 3) | o;
+        if (has(rc, ch) && own(ch, l_par) != rank) return EXPORT;
+      }
+    return DOMESTIC;
+  }
+  const bool here = own(kk, level) == rank;
+  for (uint64_t rk : recv) {
+    const bool r_here = own(rk, level) == rank;
+    if (here && !r_here) return EXPORT;
+    if (!here && r_here) return IMPORT;
+  }
+  return here ? DOMESTIC : OTHER;
+}
+
 }  // extern "C"

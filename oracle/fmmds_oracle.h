@@ -81,6 +81,11 @@ int oref_partition(const oref_tree* t, uint32_t l_par, uint32_t n_ranks, uint32_
 int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
                    uint8_t* types_out);
 
+/* The type of one source box, from the definition without lists (for
+ * sampled checks of large builds). Returns the type or minus a status. */
+int oref_box_type_one(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
+                      uint32_t level, uint32_t box);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,10 @@ def _lib():
         L.fmmds_batch_sort_items.restype = _u32
         L.fmmds_batch_free.argtypes = [_vp]
         L.fmmds_batch_free.restype = None
+        L.fmmds_partition.argtypes = [C.POINTER(TreeStruct), _u32, _u32, _vp, _vp]
+        L.fmmds_partition.restype = C.c_int
+        L.fmmds_box_types.argtypes = [C.POINTER(TreeStruct), _u32, _vp, _u32, _vp, _vp]
+        L.fmmds_box_types.restype = C.c_int
         L.fmmds_displace.argtypes = [C.POINTER(DisplaceSet), _u32, C.c_float, _vp, _vp]
         L.fmmds_displace.restype = C.c_int
         L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
@@ -123,7 +127,7 @@ def exported_symbols():
             "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
-            "fmmds_batch_free", "fmmds_displace"]
+            "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types"]
 
 
 class DisplaceSet(C.Structure):
@@ -287,6 +291,31 @@ class Tree:
     def interactions(self, l: int):
         """(offsets_ptr, entries_ptr, n_recv_boxes, n_entries) of E4 at level l."""
         return self._list(4, l)
+
+    # -- simulated partition and source box types (Section 3)
+    def partition(self, l_par: int, n_ranks: int, stream=None):
+        """Rank of every Morton index of level l_par (fmmds_partition): an
+        int32 CUDA tensor of 8^l_par entries (ranks are nonnegative)."""
+        import torch
+        out = torch.empty(1 << (3 * l_par), dtype=torch.int32, device="cuda")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        st = _lib().fmmds_partition(self._h, l_par, n_ranks, out.data_ptr(), s.cuda_stream)
+        if st != OK:
+            raise FmmdsError(st, "fmmds_partition")
+        return out
+
+    def box_types(self, l_par: int, owner, rank: int, stream=None):
+        """Source box types of `rank` (fmmds_box_types): a uint8 CUDA tensor
+        with levels 2..depth concatenated, and the per-level sizes."""
+        import torch
+        sizes = [self.n_boxes(SRC, l) for l in range(2, self.depth + 1)]
+        out = torch.empty(max(sum(sizes), 1), dtype=torch.uint8, device="cuda")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        st = _lib().fmmds_box_types(self._h, l_par, owner.data_ptr(), rank, out.data_ptr(),
+                                    s.cuda_stream)
+        if st != OK:
+            raise FmmdsError(st, "fmmds_box_types")
+        return out, sizes
 
     # -- host copies (for checks and small consumers)
     def host_perm(self, s: int) -> np.ndarray:

@@ -141,4 +141,27 @@ struct DisplaceArgs {
 };
 void launch_displace(const DisplaceArgs& a, float sigma, float* out, hipStream_t s);
 
+// ---- boxtypes.hip
+struct BoxTypeLevel {
+  uint32_t level, l_par, rank;
+  uint32_t n_recv, n_src;       // nonempty boxes of the level
+  const void* rkey;             // level keys (uint32 or uint64)
+  const void* skey;
+  const void* rkey_par;         // critical level: keys of the l_par level
+  const void* skey_par;
+  const uint32_t* rchild;       // critical level: first children (n + 1)
+  const uint32_t* schild;
+  const uint32_t* owner;        // rank of every Morton index of l_par
+  const uint32_t* e4_off;       // the level's E4 lists
+  const uint32_t* e4_ent;
+  uint32_t* flags;              // n_src words, zeroed
+  uint8_t* types;               // n_src outputs
+};
+void launch_partition(bool key64, const void* rkey, const uint32_t* rbegin, uint32_t n_boxes,
+                      uint32_t n_points, uint32_t n_ranks, uint32_t l_par, uint32_t* owner,
+                      hipStream_t s);
+void launch_fill_u8(uint8_t* p, uint32_t n, uint8_t v, hipStream_t s);
+void launch_types_crit(bool key64, const BoxTypeLevel& a, hipStream_t s);
+void launch_types_deep(bool key64, const BoxTypeLevel& a, hipStream_t s);
+
 }  // namespace fmmds

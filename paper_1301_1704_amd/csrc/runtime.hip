@@ -1271,6 +1271,72 @@ fmmds_status list_query(const fmmds_tree* t, int kind, uint32_t level, const uin
   return FMMDS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Simulated partition and source box types (fmmds_partition, fmmds_box_types).
+// ---------------------------------------------------------------------------
+bool par_level_ok(const fmmds_tree* t, uint32_t l_par) {
+  return l_par >= 3 && l_par <= t->depth && l_par <= 10;
+}
+
+fmmds_status partition(const fmmds_tree* t, uint32_t l_par, uint32_t n_ranks, uint32_t* owner,
+                       hipStream_t st) {
+  if (!t || !t->impl || !owner || n_ranks == 0) return FMMDS_ERR_ARG;
+  if (!par_level_ok(t, l_par)) return FMMDS_ERR_LEVEL;
+  const fmmds_level& rl = t->recv[l_par];
+  launch_partition(t->key_bits == 64, rl.key, rl.begin, rl.n, t->n_recv, n_ranks, l_par, owner,
+                   st);
+  return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
+}
+
+fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
+                       uint8_t* types, hipStream_t st) {
+  if (!t || !t->impl || !owner || !types) return FMMDS_ERR_ARG;
+  if (!par_level_ok(t, l_par)) return FMMDS_ERR_LEVEL;
+  const TreeImpl* impl = (const TreeImpl*)t->impl;
+  const bool key64 = t->key_bits == 64;
+  const uint32_t l_crit = l_par - 1;
+  uint32_t n_max = 1;
+  for (uint32_t l = l_crit; l <= t->depth; ++l) n_max = std::max(n_max, t->src[l].n);
+  // flags are zeroed in whole 16-byte words
+  void* flags = cache_alloc(round_up((size_t)n_max, 4) * 4, st);
+  if (!flags) return FMMDS_ERR_NOMEM;
+  size_t at = 0;
+  for (uint32_t l = 2; l <= t->depth; ++l) {
+    const uint32_t ns = t->src[l].n;
+    uint8_t* ty = types + at;
+    at += ns;
+    if (l < l_crit) {
+      launch_fill_u8(ty, ns, FMMDS_BOX_DOMESTIC, st);
+      continue;
+    }
+    launch_zero(flags, round_up((size_t)ns, 4) * 4, st);
+    BoxTypeLevel a{};
+    a.level = l;
+    a.l_par = l_par;
+    a.rank = rank;
+    a.n_recv = t->recv[l].n;
+    a.n_src = ns;
+    a.rkey = t->recv[l].key;
+    a.skey = t->src[l].key;
+    a.owner = owner;
+    a.e4_off = impl->lists[l].off[1];
+    a.e4_ent = impl->lists[l].ent[1];
+    a.flags = (uint32_t*)flags;
+    a.types = ty;
+    if (l == l_crit) {
+      a.rkey_par = t->recv[l_par].key;
+      a.skey_par = t->src[l_par].key;
+      a.rchild = t->recv[l].child;
+      a.schild = t->src[l].child;
+      launch_types_crit(key64, a, st);
+    } else {
+      launch_types_deep(key64, a, st);
+    }
+  }
+  cache_release(flags, st);
+  return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
+}
+
 }  // namespace
 }  // namespace fmmds
 
@@ -1362,6 +1428,16 @@ fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, flo
   }
   if (hipGetLastError() != hipSuccess) return FMMDS_ERR_DEVICE;
   return FMMDS_OK;
+}
+
+fmmds_status fmmds_partition(const fmmds_tree* t, uint32_t l_par, uint32_t n_ranks,
+                             uint32_t* owner, void* stream) {
+  return fmmds::partition(t, l_par, n_ranks, owner, (hipStream_t)stream);
+}
+
+fmmds_status fmmds_box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owner,
+                             uint32_t rank, uint8_t* types, void* stream) {
+  return fmmds::box_types(t, l_par, owner, rank, types, (hipStream_t)stream);
 }
 
 void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,

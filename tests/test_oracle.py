@@ -363,3 +363,18 @@ def test_box_types_exchange_symmetry_shared(oracle_lib):
             elsewhere = [types[r][l - 2][i] for r in range(R) if r != own[i]]
             assert on_owner in (0, 1) and all(v in (2, 4) for v in elsewhere)
             assert (on_owner == 1) == any(v == 2 for v in elsewhere)
+
+
+def test_one_box_type_agrees_with_whole_levels(oracle_lib):
+    """The per-box evaluation (no lists) used for sampled checks of large
+    builds gives the pinned whole-level result."""
+    src = I.sphere_cluster_points(81, 82, 3000)
+    recv = I.uniform_points(83, 2500)
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=6)
+    for l_par, R in ((3, 3), (4, 5)):
+        owner = t.partition(l_par, R)
+        for rank in (0, R - 1):
+            types = t.box_types(l_par, owner, rank)
+            for l in range(2, 7):
+                for k in range(0, types[l - 2].size, 7):
+                    assert t.box_type_one(l_par, owner, rank, l, k) == types[l - 2][k], (l, k)
