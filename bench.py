@@ -247,6 +247,43 @@ def bench_batched(F, torch, args):
     return res
 
 
+def bench_box_types(F, torch, src, recv, kw, n_ranks=64, l_par=4):
+    """Source box types (Section 3.1) of every rank of a simulated partition
+    (Section 3.2) of the benchmark build: fmmds_partition once, then
+    fmmds_box_types for each of the ranks; the tree is built beforehand and
+    stays resident."""
+    t = F.build(src, recv, **kw)
+    torch.cuda.synchronize()
+    owner = t.partition(l_par, n_ranks)
+    out, sizes = t.box_types(l_par, owner, 0)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    owner = t.partition(l_par, n_ranks)
+    e1.record()
+    counts = []
+    for r in range(n_ranks):
+        out, _ = t.box_types(l_par, owner, r)
+        if r in (0, n_ranks // 2):
+            counts.append(out)
+    e2.record()
+    torch.cuda.synchronize()
+    part_ms, all_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    names = ["domestic", "export", "import", "root", "other"]
+    c0 = torch.bincount(counts[0][:sum(sizes)].to(torch.int64), minlength=5).tolist()
+    boxes = sum(sizes)
+    t.free()
+    res = {"workload": f"partition level {l_par}, {n_ranks} ranks, source boxes of levels "
+                       f"2..{len(sizes) + 1} of the benchmark build",
+           "ranks": n_ranks, "l_par": l_par, "source_boxes": boxes,
+           "partition_ms": part_ms, "ms_all_ranks": all_ms, "ms_per_rank": all_ms / n_ranks,
+           "box_types_per_s": boxes * n_ranks / (all_ms * 1e-3),
+           "rank0_counts": dict(zip(names, c0))}
+    log(f"box types: {all_ms / n_ranks:.3f} ms per rank ({n_ranks} ranks, l_par {l_par}), "
+        f"partition {part_ms:.3f} ms; rank 0: {res['rank0_counts']}")
+    return res
+
+
 def bench_serving(F, torch, args):
     """Continuous-batching serving of rebuild requests from 64 moving particle
     systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
@@ -301,6 +338,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-box-types", action="store_true",
+                    help="skip the partition / source box type measurement")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -418,6 +457,8 @@ def main():
                                "avg_us": round(1e3 * b["total_ms"] / b["launches"], 2),
                                "GBps": round(b["bytes"] / (b["total_ms"] * 1e6), 1)}
                            for k, b in breakdown.items()}
+    if not args.no_box_types and args.workload != "small":
+        line["box_types"] = bench_box_types(F, torch, src, recv, kw)
     if not args.no_batch:
         line["batched"] = bench_batched(F, torch, args)
     if not args.no_serving:

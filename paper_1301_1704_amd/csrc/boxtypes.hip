@@ -19,8 +19,9 @@
 //
 // The E4 lists of the build give "r has k in E4(r)" directly, so the marks
 // are made by the receivers: each receiver box reads its list and sets bits
-// on the source boxes it names. Receivers whose whole M2L region lies inside
-// l_par boxes of their own rank cannot set any bit and skip the list.
+// on the source boxes it names. A receiver whose whole M2L region lies in
+// l_par boxes of its own rank cannot set any bit, nor can a receiver of
+// another rank whose region has no box of this rank; both skip the list.
 #include "../../include/fmmds.h"
 #include "device.h"
 #include "internal.h"
@@ -121,16 +122,19 @@ __global__ __launch_bounds__(256) void k_mark_deep(
     lo[d] = max(0, (2 * (p - 1)) >> sh);
     hi[d] = min(top, (2 * (p + 1) + 1) >> sh);
   }
-  bool uniform = true;
-  for (int32_t z = lo[2]; z <= hi[2] && uniform; ++z)
-    for (int32_t y = lo[1]; y <= hi[1] && uniform; ++y)
-      for (int32_t x = lo[0]; x <= hi[0] && uniform; ++x) {
-        const uint64_t m = spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) |
-                           (spread3((uint32_t)z) << 2);
-        uniform = owner[m] == o_r;
-      }
-  if (uniform) return;
+  // Marks need a region with another rank than r's; a receiver of another
+  // rank marks only boxes of `rank`, so its region must also touch `rank`.
   const bool r_here = o_r == rank;
+  bool mixed = false, touches = r_here;
+  for (int32_t z = lo[2]; z <= hi[2]; ++z)
+    for (int32_t y = lo[1]; y <= hi[1]; ++y)
+      for (int32_t x = lo[0]; x <= hi[0]; ++x) {
+        const uint32_t o = owner[spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) |
+                                 (spread3((uint32_t)z) << 2)];
+        mixed |= o != o_r;
+        touches |= o == rank;
+      }
+  if (!mixed || !touches) return;
   for (uint32_t i = e4_off[r]; i < e4_off[r + 1]; ++i) {
     const uint32_t k = e4_ent[i];
     const bool k_here = owner[(uint64_t)skey[k] >> (3 * sh)] == rank;
