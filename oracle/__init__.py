@@ -67,6 +67,7 @@ def lib():
         L.oref_partition.argtypes = [vp, u32, u32, vp]
         L.oref_box_types.argtypes = [vp, u32, vp, u32, vp]
         L.oref_box_type_one.argtypes = [vp, u32, vp, u32, u32, u32]
+        L.oref_near_field.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -208,3 +209,16 @@ class OracleTree:
         if v < 0:
             raise OracleError(-v, "oref_box_type_one")
         return int(v)
+
+    def near_field(self, charges=None):
+        """(phi, abs_sum) per receiver point in original order, FP64: the
+        Laplace sum over the source points of the E2 boxes of each receiver
+        point's finest-level box (Algorithm 2)."""
+        m = self.n_points(RECV)
+        phi = np.empty(m, dtype=np.float64)
+        a = np.empty(m, dtype=np.float64)
+        q = None if charges is None else np.ascontiguousarray(charges, dtype=np.float32)
+        st = lib().oref_near_field(self._h, None if q is None else _ptr(q), _ptr(phi), _ptr(a))
+        if st != OK:
+            raise OracleError(st, "oref_near_field")
+        return phi, a

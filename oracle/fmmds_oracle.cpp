@@ -604,4 +604,46 @@ int oref_box_type_one(const oref_tree* t, uint32_t l_par, const uint32_t* owner,
   return here ? DOMESTIC : OTHER;
 }
 
+// ---------------------------------------------------------------------------
+// Near-field sum over E2 (Algorithm 2 and a Laplace kernel).
+// ---------------------------------------------------------------------------
+
+// For every receiver point y (original order): phi = sum of q_i / |x_i - y|
+// over the source points x_i of the E2 boxes of y's box at the finest level
+// (Algorithm 2 gathers exactly these points), pairs at distance zero left
+// out; abs_sum = the same with |q_i|. Charges in original source order, NULL
+// for unit charges. FP64 from the FP32 coordinates; needs the lists.
+int oref_near_field(const oref_tree* t, const float* charges, double* phi, double* abs_sum) {
+  if (!t || !phi || !abs_sum || !t->has_lists) return OREF_ERR_ARG;
+  const uint32_t D = t->depth;
+  const PointSet& S = t->set(0);
+  const PointSet& R = t->set(1);
+  const Level& rl = R.lv[D];
+  const Level& sl = S.lv[D];
+  const List& e2 = t->e2[D];
+  for (size_t b = 0; b + 1 < rl.begin.size(); ++b) {
+    for (uint32_t k = rl.begin[b]; k < rl.begin[b + 1]; ++k) {
+      const double y[3] = {R.sorted_xyz[3 * (size_t)k], R.sorted_xyz[3 * (size_t)k + 1],
+                           R.sorted_xyz[3 * (size_t)k + 2]};
+      double f = 0.0, a = 0.0;
+      for (uint32_t e = e2.off[b]; e < e2.off[b + 1]; ++e) {
+        const uint32_t sb = e2.ent[e];
+        for (uint32_t i = sl.begin[sb]; i < sl.begin[sb + 1]; ++i) {
+          const double dx = (double)S.sorted_xyz[3 * (size_t)i] - y[0];
+          const double dy = (double)S.sorted_xyz[3 * (size_t)i + 1] - y[1];
+          const double dz = (double)S.sorted_xyz[3 * (size_t)i + 2] - y[2];
+          const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+          if (d == 0.0) continue;
+          const double q = charges ? (double)charges[S.perm[i]] : 1.0;
+          f += q / d;
+          a += std::fabs(q) / d;
+        }
+      }
+      phi[R.perm[k]] = f;
+      abs_sum[R.perm[k]] = a;
+    }
+  }
+  return OREF_OK;
+}
+
 }  // extern "C"

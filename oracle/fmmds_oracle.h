@@ -81,6 +81,13 @@ int oref_partition(const oref_tree* t, uint32_t l_par, uint32_t n_ranks, uint32_
 int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,
                    uint8_t* types_out);
 
+/* Near-field sum (Algorithm 2 with a Laplace kernel): for every receiver
+ * point y, in original order, phi[y] = sum of q_i / |x_i - y| over the source
+ * points of the E2 boxes of y's box at the finest level (pairs at distance 0
+ * left out) and abs_sum[y] = the same with |q_i|; FP64. charges: n_src, in
+ * original source order, or NULL for unit charges. Needs with_lists. */
+int oref_near_field(const oref_tree* t, const float* charges, double* phi, double* abs_sum);
+
 /* The type of one source box, from the definition without lists (for
  * sampled checks of large builds). Returns the type or minus a status. */
 int oref_box_type_one(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,

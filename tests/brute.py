@@ -188,3 +188,26 @@ def box_types(src, recv, L: int, depth: int, l_par: int, owner, rank: int):
                     types.append(2 if need else 4)
         out.append(types)
     return out
+
+
+# ------------------------------------------------------------- near field
+
+def near_field(src, recv, depth: int, charges=None):
+    """For every receiver point, in input order: the sum of q / |x - y| over
+    the source points whose finest-level box is within Chebyshev distance 1
+    of the receiver point's box (the E2 neighborhood), distance-0 pairs left
+    out; FP64. No tables or lists: boxes from exact coordinates."""
+    sc = [exact_coords(p, depth) for p in src]
+    out = []
+    for y in recv:
+        cy = exact_coords(y, depth)
+        f = 0.0
+        for i, x in enumerate(src):
+            if max(abs(sc[i][d] - cy[d]) for d in range(3)) > 1:
+                continue
+            r = float(np.sqrt(sum((float(x[d]) - float(y[d])) ** 2 for d in range(3))))
+            if r == 0.0:
+                continue
+            f += (1.0 if charges is None else float(charges[i])) / r
+        out.append(f)
+    return np.asarray(out)

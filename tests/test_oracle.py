@@ -378,3 +378,60 @@ def test_one_box_type_agrees_with_whole_levels(oracle_lib):
             for l in range(2, 7):
                 for k in range(0, types[l - 2].size, 7):
                     assert t.box_type_one(l_par, owner, rank, l, k) == types[l - 2][k], (l, k)
+
+
+# ------------------------------------------------------------- near field
+
+NEAR_CASES = [
+    ("shared", I.uniform_points(101, 300), None, 3),
+    ("separate", I.sphere_cluster_points(102, 103, 250), I.uniform_points(104, 200), 4),
+]
+
+
+@pytest.mark.parametrize("name,src,recv,L", NEAR_CASES, ids=[c[0] for c in NEAR_CASES])
+@pytest.mark.parametrize("charged", [False, True])
+def test_near_field_by_brute_force(oracle_lib, name, src, recv, L, charged):
+    """Algorithm 2's gather plus the Laplace kernel, against the sum over
+    every source point in the receiver's E2 neighborhood found from exact
+    box coordinates (FP64 both; only the summation order differs)."""
+    q = I.uniform_points(105, src.shape[0])[:, 0] - 0.5 if charged else None
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L)
+    phi, a = t.near_field(q)
+    rp = src if recv is None else recv
+    exp = brute.near_field([tuple(p) for p in src], [tuple(p) for p in rp], L, q)
+    assert np.allclose(phi, exp, rtol=1e-12, atol=1e-12 * a.max())
+    assert np.all(a >= np.abs(phi) * (1 - 1e-12))
+
+
+def test_near_field_special_cases(oracle_lib):
+    """One source point: each receiver in a neighboring box sees exactly
+    q / r, the others 0; duplicated points do not see themselves."""
+    src = np.asarray([[0.30, 0.30, 0.30]], dtype=np.float32)
+    recv = np.asarray([[0.31, 0.29, 0.30], [0.55, 0.30, 0.30], [0.30, 0.30, 0.30],
+                       [0.45, 0.45, 0.45]], dtype=np.float32)
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=3)
+    phi, _ = t.near_field(np.asarray([2.0], dtype=np.float32))
+    d0 = np.sqrt(np.sum((recv[0].astype(np.float64) - src[0]) ** 2))
+    d3 = np.sqrt(np.sum((recv[3].astype(np.float64) - src[0]) ** 2))
+    # boxes at level 3 have side 1/8: 0.30 -> 2, 0.55 -> 4 (two boxes away), 0.45 -> 3
+    assert phi[0] == pytest.approx(2.0 / d0, rel=1e-15)
+    assert phi[1] == 0.0
+    assert phi[2] == 0.0  # same position as the source
+    assert phi[3] == pytest.approx(2.0 / d3, rel=1e-15)
+
+
+def test_near_field_pair_symmetry_shared(oracle_lib):
+    """Shared sets: E2 is symmetric, so with unit charges the total over all
+    receivers counts every near pair twice: equal to twice the pair sum."""
+    p = I.sphere_cluster_points(106, 107, 800)
+    t = oracle_lib.OracleTree(p, key_bits=64, max_level=4)
+    phi, _ = t.near_field()
+    keys = oracle_lib.point_keys(p, 4)
+    c = np.stack([np.floor(p[:, d].astype(np.float64) * 16) for d in range(3)], axis=1)
+    total = 0.0
+    for i in range(len(p)):
+        near = np.max(np.abs(c[i + 1:] - c[i]), axis=1) <= 1
+        d = np.sqrt(np.sum((p[i + 1:][near].astype(np.float64) - p[i]) ** 2, axis=1))
+        total += np.sum(1.0 / d[d > 0])
+    assert keys.size == len(p)
+    assert phi.sum() == pytest.approx(2.0 * total, rel=1e-12)
