@@ -265,6 +265,26 @@ fmmds_status fmmds_partition(const fmmds_tree* t, uint32_t l_par, uint32_t n_ran
 fmmds_status fmmds_box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owner,
                              uint32_t rank, uint8_t* types, void* stream);
 
+/*
+ * Near-field sum, the first consumer of the lists (Algorithm 2 with a
+ * Laplace kernel, the direct part of the FMM sum of Section 1.2): for every
+ * receiver point y, phi(y) = sum of q_i / |x_i - y| over the source points
+ * x_i of the E2 boxes of y's box at the finest level (exactly the points
+ * Algorithm 2 gathers), pairs at distance zero left out. FP32 arithmetic.
+ *   charges: device, n_src values in the original source order, or NULL
+ *            for unit charges.
+ *   phi:     device, n_recv values, written in the original receiver order
+ *            (through the receiver permutation).
+ *   n_pairs: device uint64 or NULL; if set, the number of (receiver, source)
+ *            pairs visited (distance-zero pairs included) is added to it.
+ *   stream:  hipStream_t the work is ordered on (NULL = null stream); the
+ *            tree must be complete on it. Returns at once.
+ * Uses a temporary device buffer of 16 bytes per source point (the library's
+ * cache). Works on batch views too (all indices set-local).
+ */
+fmmds_status fmmds_near_field(const fmmds_tree* t, const float* charges, float* phi,
+                              uint64_t* n_pairs, void* stream);
+
 /* Memory the library allocates itself (opt->alloc == NULL) is cached after
  * release, per device, and reused by later builds of similar size. This call
  * synchronizes every device the cache holds memory of and returns all cached

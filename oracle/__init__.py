@@ -68,6 +68,8 @@ def lib():
         L.oref_box_types.argtypes = [vp, u32, vp, u32, vp]
         L.oref_box_type_one.argtypes = [vp, u32, vp, u32, u32, u32]
         L.oref_near_field.argtypes = [vp, vp, vp, vp]
+        L.oref_near_field_one.argtypes = [vp, vp, u32, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -222,3 +224,14 @@ class OracleTree:
         if st != OK:
             raise OracleError(st, "oref_near_field")
         return phi, a
+
+    def near_field_one(self, j: int, charges=None):
+        """(phi, abs_sum) of receiver point j (original index), FP64, from
+        the definition without lists."""
+        q = None if charges is None else np.ascontiguousarray(charges, dtype=np.float32)
+        f, a = C.c_double(), C.c_double()
+        st = lib().oref_near_field_one(self._h, None if q is None else _ptr(q), j,
+                                       C.byref(f), C.byref(a))
+        if st != OK:
+            raise OracleError(st, "oref_near_field_one")
+        return f.value, a.value

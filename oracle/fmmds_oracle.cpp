@@ -646,4 +646,44 @@ int oref_near_field(const oref_tree* t, const float* charges, double* phi, doubl
   return OREF_OK;
 }
 
+// The near-field sum of one receiver point (original index j) from the
+// definition, without lists: the source boxes at Chebyshev distance <= 1 of
+// the point's finest-level box are looked up among the nonempty source boxes.
+int oref_near_field_one(const oref_tree* t, const float* charges, uint32_t j, double* phi,
+                        double* abs_sum) {
+  if (!t || !phi || !abs_sum) return OREF_ERR_ARG;
+  const PointSet& S = t->set(0);
+  const PointSet& R = t->set(1);
+  if (j >= R.perm.size()) return OREF_ERR_ARG;
+  const uint32_t D = t->depth;
+  // position of j in the sorted receivers, and its coordinates
+  const size_t k = std::find(R.perm.begin(), R.perm.end(), j) - R.perm.begin();
+  const double y[3] = {R.sorted_xyz[3 * k], R.sorted_xyz[3 * k + 1], R.sorted_xyz[3 * k + 2]};
+  int64_t cy[3];
+  deinterleave(R.sorted_key[k] >> (3 * (t->max_level - D)), D, cy);
+  const Level& sl = S.lv[D];
+  Lookup look(sl, D, false);
+  double f = 0.0, a = 0.0;
+  int64_t c[3];
+  for (c[2] = cy[2] - 1; c[2] <= cy[2] + 1; ++c[2])
+    for (c[1] = cy[1] - 1; c[1] <= cy[1] + 1; ++c[1])
+      for (c[0] = cy[0] - 1; c[0] <= cy[0] + 1; ++c[0]) {
+        const int64_t sb = look.rank(c);
+        if (sb < 0) continue;
+        for (uint32_t i = sl.begin[sb]; i < sl.begin[sb + 1]; ++i) {
+          const double dx = (double)S.sorted_xyz[3 * (size_t)i] - y[0];
+          const double dy = (double)S.sorted_xyz[3 * (size_t)i + 1] - y[1];
+          const double dz = (double)S.sorted_xyz[3 * (size_t)i + 2] - y[2];
+          const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+          if (d == 0.0) continue;
+          const double q = charges ? (double)charges[S.perm[i]] : 1.0;
+          f += q / d;
+          a += std::fabs(q) / d;
+        }
+      }
+  *phi = f;
+  *abs_sum = a;
+  return OREF_OK;
+}
+
 }  // extern "C"

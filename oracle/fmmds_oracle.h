@@ -88,6 +88,11 @@ int oref_box_types(const oref_tree* t, uint32_t l_par, const uint32_t* owner, ui
  * original source order, or NULL for unit charges. Needs with_lists. */
 int oref_near_field(const oref_tree* t, const float* charges, double* phi, double* abs_sum);
 
+/* The same for one receiver point (original index j), from the definition
+ * without lists (for sampled checks of large builds). */
+int oref_near_field_one(const oref_tree* t, const float* charges, uint32_t j, double* phi,
+                        double* abs_sum);
+
 /* The type of one source box, from the definition without lists (for
  * sampled checks of large builds). Returns the type or minus a status. */
 int oref_box_type_one(const oref_tree* t, uint32_t l_par, const uint32_t* owner, uint32_t rank,

@@ -103,6 +103,8 @@ def _lib():
         L.fmmds_partition.restype = C.c_int
         L.fmmds_box_types.argtypes = [C.POINTER(TreeStruct), _u32, _vp, _u32, _vp, _vp]
         L.fmmds_box_types.restype = C.c_int
+        L.fmmds_near_field.argtypes = [C.POINTER(TreeStruct), _vp, _vp, _vp, _vp]
+        L.fmmds_near_field.restype = C.c_int
         L.fmmds_displace.argtypes = [C.POINTER(DisplaceSet), _u32, C.c_float, _vp, _vp]
         L.fmmds_displace.restype = C.c_int
         L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
@@ -127,7 +129,8 @@ def exported_symbols():
             "fmmds_profile_read", "fmmds_status_string", "fmmds_batch_create",
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
-            "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types"]
+            "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types",
+            "fmmds_near_field"]
 
 
 class DisplaceSet(C.Structure):
@@ -316,6 +319,26 @@ class Tree:
         if st != OK:
             raise FmmdsError(st, "fmmds_box_types")
         return out, sizes
+
+    # -- near-field sum over E2 (Algorithm 2 with a Laplace kernel)
+    def near_field(self, charges=None, count_pairs: bool = False, stream=None):
+        """phi per receiver point (original order) as a float32 CUDA tensor,
+        and the number of pairs visited (if count_pairs, else None)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        phi = torch.empty(self.n_recv, dtype=torch.float32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda") if count_pairs else None
+        if charges is not None:
+            if charges.dtype != torch.float32 or not charges.is_cuda or \
+                    charges.numel() != self.n_src:
+                raise ValueError("charges: float32 CUDA tensor of n_src values")
+            charges = charges.contiguous()
+        st = _lib().fmmds_near_field(self._h, None if charges is None else charges.data_ptr(),
+                                     phi.data_ptr(), None if cnt is None else cnt.data_ptr(),
+                                     s.cuda_stream)
+        if st != OK:
+            raise FmmdsError(st, "fmmds_near_field")
+        return phi, (None if cnt is None else cnt)
 
     # -- host copies (for checks and small consumers)
     def host_perm(self, s: int) -> np.ndarray:

@@ -1337,6 +1337,21 @@ fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owne
   return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
 }
 
+fmmds_status near_field(const fmmds_tree* t, const float* charges, float* phi,
+                        uint64_t* n_pairs, hipStream_t st) {
+  if (!t || !t->impl || !phi) return FMMDS_ERR_ARG;
+  const TreeImpl* impl = (const TreeImpl*)t->impl;
+  const uint32_t D = t->depth;
+  void* src4 = cache_alloc((size_t)t->n_src * 16, st);
+  if (!src4) return FMMDS_ERR_NOMEM;
+  launch_pack_sources(t->src_sorted_xyz, t->src_perm, charges, t->n_src, (float4*)src4, st);
+  launch_near_field(t->n_recv, t->recv[D].n, t->recv[D].begin, t->recv_sorted_xyz, t->recv_perm,
+                    impl->lists[D].off[0], impl->lists[D].ent[0], t->src[D].begin,
+                    (const float4*)src4, phi, (unsigned long long*)n_pairs, st);
+  cache_release(src4, st);
+  return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
+}
+
 }  // namespace
 }  // namespace fmmds
 
@@ -1438,6 +1453,11 @@ fmmds_status fmmds_partition(const fmmds_tree* t, uint32_t l_par, uint32_t n_ran
 fmmds_status fmmds_box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owner,
                              uint32_t rank, uint8_t* types, void* stream) {
   return fmmds::box_types(t, l_par, owner, rank, types, (hipStream_t)stream);
+}
+
+fmmds_status fmmds_near_field(const fmmds_tree* t, const float* charges, float* phi,
+                              uint64_t* n_pairs, void* stream) {
+  return fmmds::near_field(t, charges, phi, n_pairs, (hipStream_t)stream);
 }
 
 void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,

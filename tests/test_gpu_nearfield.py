@@ -1,0 +1,139 @@
+"""GPU parity of the near-field sum over E2 (Algorithm 2 gather with a
+Laplace kernel): fmmds_near_field through the C ABI against the FP64 oracle.
+
+Tolerance, from the FP32 arithmetic: each term q / r carries a few units of
+rounding (two roundings in the differences, the squared distance, rsqrt and
+the product), and a recursive sum of n terms adds at most (n - 1) units of
+2^-24 times the sum of the magnitudes. With n at most 27 times the largest
+source box of the finest level, every receiver must satisfy
+    |phi_gpu - phi_fp64| <= (n + 8) * 2^-24 * sum |q| / r."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import parity
+from paper_1301_1704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_1704_amd as F
+    if not os.path.exists(F.LIB_PATH):
+        from paper_1301_1704_amd import _compile
+        _compile.build()
+    F._lib()
+    return F
+
+
+def _tol(o, a):
+    n = 27 * o.max_occupancy(0, o.depth)
+    return (n + 8) * 2.0 ** -24 * a
+
+
+CASES = [
+    ("shared-uniform", lambda: (I.uniform_points(121, 40000), None, None), 6, 0),
+    ("separate-charged", lambda: (I.uniform_points(122, 30000), I.sphere_cluster_points(123, 124, 35000),
+                                  I.uniform_points(125, 30000)[:, 2] - 0.5), 7, 0),
+    ("clustered-s64", lambda: (I.sphere_cluster_points(126, 127, 60000), None,
+                               I.uniform_points(128, 60000)[:, 0]), 9, 64),
+]
+
+
+@pytest.mark.parametrize("name,make,L,s", CASES, ids=[c[0] for c in CASES])
+def test_near_field_matches_oracle(F, oracle_lib, name, make, L, s):
+    import torch
+    src, recv, q = make()
+    _say(f"case {name} L={L} s={s}")
+    g = F.build(parity.to_gpu(src), None if recv is None else parity.to_gpu(recv),
+                max_level=L, key_bits=64, cluster_s=s)
+    qd = None if q is None else torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda()
+    phi, cnt = g.near_field(qd, count_pairs=True)
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=L, cluster_s=s)
+    assert g.depth == o.depth
+    ref, a = o.near_field(q)
+    got = phi.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= _tol(o, a)), np.max(np.abs(got - ref) / np.maximum(a, 1e-30))
+    # pairs visited: receiver points of each box times the source points of its E2 boxes
+    D = o.depth
+    off, ent = o.list(2, D)
+    sb = o.begin(0, D).astype(np.int64)
+    rb = o.begin(1, D).astype(np.int64)
+    per_src = np.diff(sb)
+    cs = np.concatenate([[0], np.cumsum(per_src[ent])])
+    per_box = cs[off[1:].astype(np.int64)] - cs[off[:-1].astype(np.int64)]
+    assert int(cnt.item()) == int(np.sum(per_box * np.diff(rb)))
+    g.free()
+    o.close()
+
+
+def test_batch_view_equals_plain_build(F):
+    import torch
+    sizes = [7000, 2000, 15000]
+    pts = [I.sphere_cluster_points(131 + i, 132, n) for i, n in enumerate(sizes)]
+    lev = np.asarray([5, 3, 6], np.uint8)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = F.Batch(off, lev)
+    b.launch(parity.to_gpu(np.concatenate(pts)))
+    b.wait()
+    for i in range(3):
+        q = torch.from_numpy(I.uniform_points(140 + i, sizes[i])[:, 1].copy()).cuda()
+        p1, _ = b.tree(i).near_field(q)
+        alone = F.build(parity.to_gpu(pts[i]), None, max_level=int(lev[i]), key_bits=64)
+        p2, _ = alone.near_field(q)
+        torch.cuda.synchronize()
+        assert torch.equal(p1, p2), i
+        alone.free()
+    b.free()
+
+
+def test_isolated_points_and_duplicates(F):
+    """Points with no neighbor box get 0; duplicated points do not see
+    themselves (distance zero) but do see their other copies' neighbors."""
+    import torch
+    pts = np.asarray([[0.1, 0.1, 0.1], [0.9, 0.9, 0.9], [0.9, 0.9, 0.9], [0.91, 0.9, 0.9]],
+                     dtype=np.float32)
+    g = F.build(parity.to_gpu(pts), None, max_level=4, key_bits=64)
+    phi, cnt = g.near_field(count_pairs=True)
+    torch.cuda.synchronize()
+    p = phi.cpu().numpy()
+    d = np.float64(np.float32(0.91) - np.float32(0.9))
+    assert p[0] == 0.0
+    assert p[1] == pytest.approx(1.0 / d, rel=1e-6) and p[2] == p[1]
+    assert p[3] == pytest.approx(2.0 / d, rel=1e-6)
+    assert int(cnt.item()) == 1 + 3 * 3
+    g.free()
+
+
+@pytest.mark.slow
+def test_full_uniform_2x2p24_L8_sampled(F, oracle_lib):
+    """The benchmark build: sampled receivers against the oracle's per-point
+    definition (no lists), same tolerance."""
+    import torch
+    c = I.config_plain_uniform()
+    _say("case near field, full uniform 2x2^24 L8")
+    g = F.build(parity.to_gpu(c["src"]), parity.to_gpu(c["recv"]), max_level=8, key_bits=64)
+    q = I.uniform_points(150, c["src"].shape[0])[:, 0] - 0.5
+    phi, _ = g.near_field(torch.from_numpy(np.ascontiguousarray(q)).cuda())
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    o = oracle_lib.OracleTree(c["src"], c["recv"], key_bits=64, max_level=8, with_lists=False)
+    n = 27 * o.max_occupancy(0, 8)
+    rng = np.random.default_rng(9)
+    for j in rng.choice(got.size, size=400, replace=False):
+        f, a = o.near_field_one(int(j), q)
+        assert abs(float(got[j]) - f) <= (n + 8) * 2.0 ** -24 * a, j
+    g.free()
+    o.close()

@@ -435,3 +435,17 @@ def test_near_field_pair_symmetry_shared(oracle_lib):
         total += np.sum(1.0 / d[d > 0])
     assert keys.size == len(p)
     assert phi.sum() == pytest.approx(2.0 * total, rel=1e-12)
+
+
+def test_near_field_one_point_agrees(oracle_lib):
+    """The per-point evaluation (no lists) used for sampled checks of large
+    builds gives the pinned whole-array result."""
+    src = I.sphere_cluster_points(108, 109, 4000)
+    recv = I.uniform_points(110, 3000)
+    q = I.uniform_points(111, 4000)[:, 1] - 0.3
+    t = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=5)
+    phi, a = t.near_field(q)
+    for j in range(0, 3000, 37):
+        f1, a1 = t.near_field_one(j, q)
+        assert f1 == pytest.approx(phi[j], rel=1e-12, abs=1e-12 * a[j])
+        assert a1 == pytest.approx(a[j], rel=1e-12)
