@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/sec full FMM data-structure build at N=M=2^24; batched builds/sec vs plain"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -284,6 +285,35 @@ def bench_box_types(F, torch, src, recv, kw, n_ranks=64, l_par=4):
     return res
 
 
+def bench_near_field(F, torch, src, recv, kw, reps=5):
+    """Near-field Laplace sum over the E2 lists of the benchmark build (one
+    charge per source point): pairs per second and FP32 rate, 9 flops per
+    pair (3 differences, 3 multiply-adds for r^2, rsqrt, the product, the
+    sum), against the FP32 vector peak."""
+    t = F.build(src, recv, **kw)
+    q = torch.rand(src.shape[0], dtype=torch.float32, device="cuda") - 0.5
+    torch.cuda.synchronize()
+    phi, cnt = t.near_field(q, count_pairs=True)  # warm-up, and the pair count
+    torch.cuda.synchronize()
+    pairs = int(cnt.item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        t.near_field(q)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    t.free()
+    tflops = 9.0 * pairs / (ms * 1e-3) / 1e12
+    res = {"workload": "unit-cube charges in [-0.5, 0.5), receivers of the benchmark build, "
+                       "finest-level E2 lists", "pairs": pairs, "ms": ms,
+           "pairs_per_s": pairs / (ms * 1e-3), "tflops_fp32": tflops,
+           "peak_tflops_fp32": FP32_PEAK_TFLOPS, "frac": tflops / FP32_PEAK_TFLOPS}
+    log(f"near field: {ms:.3f} ms, {pairs} pairs, {res['pairs_per_s']:.3g} pairs/s, "
+        f"{tflops:.2f} TFLOP/s FP32")
+    return res
+
+
 def bench_serving(F, torch, args):
     """Continuous-batching serving of rebuild requests from 64 moving particle
     systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
@@ -338,6 +368,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-near-field", action="store_true",
+                    help="skip the near-field sum measurement")
     ap.add_argument("--no-box-types", action="store_true",
                     help="skip the partition / source box type measurement")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -457,6 +489,8 @@ def main():
                                "avg_us": round(1e3 * b["total_ms"] / b["launches"], 2),
                                "GBps": round(b["bytes"] / (b["total_ms"] * 1e6), 1)}
                            for k, b in breakdown.items()}
+    if not args.no_near_field:
+        line["near_field"] = bench_near_field(F, torch, src, recv, kw)
     if not args.no_box_types and args.workload != "small":
         line["box_types"] = bench_box_types(F, torch, src, recv, kw)
     if not args.no_batch:
