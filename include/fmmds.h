@@ -250,8 +250,8 @@ fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, flo
  * From l_par down a box is on the rank of its l_par ancestor: on `rank` it is
  * EXPORT if a receiver box of another rank has it in its E4 list, else
  * DOMESTIC; elsewhere it is IMPORT if a receiver box of `rank` has it in its
- * E4 list, else OTHER. Uses a temporary device buffer of 4 bytes per source
- * box of the largest level (library or caller allocator, as the tree's).
+ * E4 list, else OTHER. Uses a temporary device buffer from the library's
+ * cache: 2 bytes per source box and 4 per receiver box of the largest level.
  */
 enum {
   FMMDS_BOX_DOMESTIC = 0,

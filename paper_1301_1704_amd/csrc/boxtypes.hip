@@ -18,17 +18,17 @@
 // elsewhere it is IMPORT when a receiver box of J has it in E4, else OTHER.
 //
 // The E4 lists of the build give "r has k in E4(r)" directly, so the marks
-// are made by the receivers: each receiver box reads its list and sets bits
-// on the source boxes it names. A receiver whose whole M2L region lies in
-// l_par boxes of its own rank cannot set any bit, nor can a receiver of
-// another rank whose region has no box of this rank; both skip the list.
+// are made by the receivers: a receiver reads its list and marks the source
+// boxes it names. A receiver whose whole M2L region lies in l_par boxes of
+// its own rank cannot mark anything, nor can a receiver of another rank whose
+// region has no box of this rank; only the others are listed and read.
 #include "../../include/fmmds.h"
 #include "device.h"
 #include "internal.h"
 
 namespace fmmds {
 
-constexpr uint32_t kNeededElsewhere = 1u, kNeededHere = 2u;
+constexpr uint32_t kMarkBlocks = 4096;  // step 2: 16384 waves walk the work list
 
 // Coordinate of a Morton index on one axis (bits 3b + axis).
 __device__ __forceinline__ uint32_t axis_coord(uint64_t key, int axis) {
@@ -61,19 +61,119 @@ __global__ __launch_bounds__(256) void k_fill_u8(uint8_t* __restrict__ p, uint32
   for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) p[i] = v;
 }
 
-// Critical level, receivers: a receiver box with a nonempty receiver child
-// on another rank marks every source box of its E4 list.
+// Marks are bytes in two arrays (needed elsewhere / needed here), set with
+// plain stores: every writer stores the same value, so no atomics are needed.
+//
+// Step 1 (per receiver): does the receiver have to read its E4 list? Those
+// that do are appended to a work list (one atomic per wave, at the end).
+// Critical level: receivers with a nonempty receiver child on another rank.
 template <typename KeyT>
-__global__ __launch_bounds__(256) void k_mark_crit(
-    uint32_t n_recv, const uint32_t* __restrict__ rchild, const KeyT* __restrict__ rkey_par,
-    const uint32_t* __restrict__ owner, uint32_t rank, const uint32_t* __restrict__ e4_off,
-    const uint32_t* __restrict__ e4_ent, uint32_t* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_pick_crit(uint32_t n_recv,
+                                                   const uint32_t* __restrict__ rchild,
+                                                   const KeyT* __restrict__ rkey_par,
+                                                   const uint32_t* __restrict__ owner,
+                                                   uint32_t rank, uint32_t* __restrict__ work,
+                                                   uint32_t* __restrict__ n_work) {
   const uint64_t r = blockIdx.x * 256ull + threadIdx.x;
-  if (r >= n_recv) return;
-  bool remote = false;
-  for (uint32_t c = rchild[r]; c < rchild[r + 1]; ++c) remote |= owner[(uint64_t)rkey_par[c]] != rank;
-  if (!remote) return;
-  for (uint32_t i = e4_off[r]; i < e4_off[r + 1]; ++i) atomicOr(&flags[e4_ent[i]], kNeededElsewhere);
+  bool pick = false;
+  if (r < n_recv)
+    for (uint32_t c = rchild[r]; c < rchild[r + 1]; ++c)
+      pick |= owner[(uint64_t)rkey_par[c]] != rank;
+  const uint64_t b = __ballot(pick);
+  if (!b) return;
+  uint32_t base = 0;
+  if ((threadIdx.x & 63u) == 0) base = atomicAdd(n_work, (uint32_t)__popcll(b));
+  base = (uint32_t)__builtin_amdgcn_readfirstlane(base);
+  if (pick) work[base + mbcnt(b)] = (uint32_t)r;
+}
+
+// Levels l >= l_par. The M2L region of r: per axis the level-l coordinates
+// 2(p - 1) .. 2(p + 1) + 1 around its parent coordinate p; their l_par
+// ancestors are that range shifted right by l - l_par. Marks need a region
+// with another rank than r's, and a receiver of another rank marks only boxes
+// of `rank`, so its region must also touch `rank`.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_pick_deep(uint32_t n_recv, const KeyT* __restrict__ rkey,
+                                                   uint32_t level, uint32_t l_par,
+                                                   const uint32_t* __restrict__ owner,
+                                                   uint32_t rank, uint32_t* __restrict__ work,
+                                                   uint32_t* __restrict__ n_work) {
+  const uint64_t r = blockIdx.x * 256ull + threadIdx.x;
+  bool pick = false;
+  if (r < n_recv) {
+    const uint32_t sh = level - l_par;
+    const uint64_t kr = (uint64_t)rkey[r];
+    const uint32_t o_r = owner[kr >> (3 * sh)];
+    const int32_t top = (1 << l_par) - 1;
+    int32_t lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      const int32_t p = (int32_t)(axis_coord(kr, d) >> 1);
+      lo[d] = max(0, (2 * (p - 1)) >> sh);
+      hi[d] = min(top, (2 * (p + 1) + 1) >> sh);
+    }
+    bool mixed = false, touches = o_r == rank;
+    for (int32_t z = lo[2]; z <= hi[2]; ++z)
+      for (int32_t y = lo[1]; y <= hi[1]; ++y)
+        for (int32_t x = lo[0]; x <= hi[0]; ++x) {
+          const uint32_t o = owner[spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) |
+                                   (spread3((uint32_t)z) << 2)];
+          mixed |= o != o_r;
+          touches |= o == rank;
+        }
+    pick = mixed && touches;
+  }
+  const uint64_t b = __ballot(pick);
+  if (!b) return;
+  uint32_t base = 0;
+  if ((threadIdx.x & 63u) == 0) base = atomicAdd(n_work, (uint32_t)__popcll(b));
+  base = (uint32_t)__builtin_amdgcn_readfirstlane(base);
+  if (pick) work[base + mbcnt(b)] = (uint32_t)r;
+}
+
+// Step 2: one wave per listed receiver at a time; its E4 entries (at most
+// 189) are read three 64-entry chunks at once, every load before any store
+// (on this GPU a wait for a load also waits for earlier stores). At the
+// critical level (deep == false) every entry is needed elsewhere.
+template <typename KeyT, bool DEEP>
+__global__ __launch_bounds__(256) void k_mark(const uint32_t* __restrict__ work,
+                                              const uint32_t* __restrict__ n_work,
+                                              const KeyT* __restrict__ rkey,
+                                              const KeyT* __restrict__ skey, uint32_t sh,
+                                              const uint32_t* __restrict__ owner, uint32_t rank,
+                                              const uint32_t* __restrict__ e4_off,
+                                              const uint32_t* __restrict__ e4_ent,
+                                              uint8_t* __restrict__ elsewhere,
+                                              uint8_t* __restrict__ here) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t n = *n_work;
+  const uint32_t n_waves = gridDim.x * 4;
+  for (uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6); w < n; w += n_waves) {
+    const uint32_t r = work[w];
+    const uint32_t lo = e4_off[r], hi = e4_off[r + 1];
+    const bool r_here = DEEP ? owner[(uint64_t)rkey[r] >> (3 * sh)] == rank : false;
+    uint32_t k[3];
+    bool k_here[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint32_t i = lo + 64u * c + lane;
+      k[c] = i < hi ? e4_ent[i] : 0xFFFFFFFFu;
+    }
+    if (DEEP) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        k_here[c] = k[c] != 0xFFFFFFFFu && owner[(uint64_t)skey[k[c]] >> (3 * sh)] == rank;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (k[c] == 0xFFFFFFFFu) continue;
+      if (!DEEP) {
+        elsewhere[k[c]] = 1;
+      } else {
+        if (k_here[c] && !r_here) elsewhere[k[c]] = 1;
+        if (!k_here[c] && r_here) here[k[c]] = 1;
+      }
+    }
+  }
 }
 
 // Critical level, sources: children on this rank and elsewhere.
@@ -83,7 +183,7 @@ __global__ __launch_bounds__(256) void k_types_crit(uint32_t n_src,
                                                     const KeyT* __restrict__ skey_par,
                                                     const uint32_t* __restrict__ owner,
                                                     uint32_t rank,
-                                                    const uint32_t* __restrict__ flags,
+                                                    const uint8_t* __restrict__ elsewhere,
                                                     uint8_t* __restrict__ types) {
   const uint64_t k = blockIdx.x * 256ull + threadIdx.x;
   if (k >= n_src) return;
@@ -96,51 +196,8 @@ __global__ __launch_bounds__(256) void k_types_crit(uint32_t n_src,
   uint8_t t;
   if (!on) t = FMMDS_BOX_IMPORT;
   else if (off) t = FMMDS_BOX_ROOT;
-  else t = (flags[k] & kNeededElsewhere) ? FMMDS_BOX_EXPORT : FMMDS_BOX_DOMESTIC;
+  else t = elsewhere[k] ? FMMDS_BOX_EXPORT : FMMDS_BOX_DOMESTIC;
   types[k] = t;
-}
-
-// Levels l >= l_par, receivers. The M2L region of r: per axis the level-l
-// coordinates 2(p - 1) .. 2(p + 1) + 1 around its parent coordinate p; their
-// l_par ancestors are that range shifted right by l - l_par. If every l_par
-// box there belongs to r's rank, so does every source box r names.
-template <typename KeyT>
-__global__ __launch_bounds__(256) void k_mark_deep(
-    uint32_t n_recv, const KeyT* __restrict__ rkey, const KeyT* __restrict__ skey, uint32_t level,
-    uint32_t l_par, const uint32_t* __restrict__ owner, uint32_t rank,
-    const uint32_t* __restrict__ e4_off, const uint32_t* __restrict__ e4_ent,
-    uint32_t* __restrict__ flags) {
-  const uint64_t r = blockIdx.x * 256ull + threadIdx.x;
-  if (r >= n_recv) return;
-  const uint32_t sh = level - l_par;
-  const uint64_t kr = (uint64_t)rkey[r];
-  const uint32_t o_r = owner[kr >> (3 * sh)];
-  const int32_t top = (1 << l_par) - 1;
-  int32_t lo[3], hi[3];
-  for (int d = 0; d < 3; ++d) {
-    const int32_t p = (int32_t)(axis_coord(kr, d) >> 1);
-    lo[d] = max(0, (2 * (p - 1)) >> sh);
-    hi[d] = min(top, (2 * (p + 1) + 1) >> sh);
-  }
-  // Marks need a region with another rank than r's; a receiver of another
-  // rank marks only boxes of `rank`, so its region must also touch `rank`.
-  const bool r_here = o_r == rank;
-  bool mixed = false, touches = r_here;
-  for (int32_t z = lo[2]; z <= hi[2]; ++z)
-    for (int32_t y = lo[1]; y <= hi[1]; ++y)
-      for (int32_t x = lo[0]; x <= hi[0]; ++x) {
-        const uint32_t o = owner[spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) |
-                                 (spread3((uint32_t)z) << 2)];
-        mixed |= o != o_r;
-        touches |= o == rank;
-      }
-  if (!mixed || !touches) return;
-  for (uint32_t i = e4_off[r]; i < e4_off[r + 1]; ++i) {
-    const uint32_t k = e4_ent[i];
-    const bool k_here = owner[(uint64_t)skey[k] >> (3 * sh)] == rank;
-    if (k_here && !r_here) atomicOr(&flags[k], kNeededElsewhere);
-    if (!k_here && r_here) atomicOr(&flags[k], kNeededHere);
-  }
 }
 
 template <typename KeyT>
@@ -148,14 +205,14 @@ __global__ __launch_bounds__(256) void k_types_deep(uint32_t n_src, const KeyT* 
                                                     uint32_t level, uint32_t l_par,
                                                     const uint32_t* __restrict__ owner,
                                                     uint32_t rank,
-                                                    const uint32_t* __restrict__ flags,
+                                                    const uint8_t* __restrict__ elsewhere,
+                                                    const uint8_t* __restrict__ here_mark,
                                                     uint8_t* __restrict__ types) {
   const uint64_t k = blockIdx.x * 256ull + threadIdx.x;
   if (k >= n_src) return;
   const bool here = owner[(uint64_t)skey[k] >> (3 * (level - l_par))] == rank;
-  const uint32_t f = flags[k];
-  types[k] = here ? ((f & kNeededElsewhere) ? FMMDS_BOX_EXPORT : FMMDS_BOX_DOMESTIC)
-                  : ((f & kNeededHere) ? FMMDS_BOX_IMPORT : FMMDS_BOX_OTHER);
+  types[k] = here ? (elsewhere[k] ? FMMDS_BOX_EXPORT : FMMDS_BOX_DOMESTIC)
+                  : (here_mark[k] ? FMMDS_BOX_IMPORT : FMMDS_BOX_OTHER);
 }
 
 static uint32_t grid_for(uint64_t n) {
@@ -181,34 +238,41 @@ void launch_fill_u8(uint8_t* p, uint32_t n, uint8_t v, hipStream_t s) {
                      n, v);
 }
 
+template <typename K>
+static void types_crit(const BoxTypeLevel& a, hipStream_t s) {
+  if (a.n_recv) {
+    hipLaunchKernelGGL(k_pick_crit<K>, dim3(grid_for(a.n_recv)), dim3(256), 0, s, a.n_recv,
+                       a.rchild, (const K*)a.rkey_par, a.owner, a.rank, a.work, a.n_work);
+    hipLaunchKernelGGL((k_mark<K, false>), dim3(kMarkBlocks), dim3(256), 0, s, a.work, a.n_work,
+                       (const K*)a.rkey, (const K*)a.skey, 0u, a.owner, a.rank, a.e4_off,
+                       a.e4_ent, a.elsewhere, a.here);
+  }
+  hipLaunchKernelGGL(k_types_crit<K>, dim3(grid_for(a.n_src)), dim3(256), 0, s, a.n_src,
+                     a.schild, (const K*)a.skey_par, a.owner, a.rank, a.elsewhere, a.types);
+}
+
+template <typename K>
+static void types_deep(const BoxTypeLevel& a, hipStream_t s) {
+  if (a.n_recv) {
+    hipLaunchKernelGGL(k_pick_deep<K>, dim3(grid_for(a.n_recv)), dim3(256), 0, s, a.n_recv,
+                       (const K*)a.rkey, a.level, a.l_par, a.owner, a.rank, a.work, a.n_work);
+    hipLaunchKernelGGL((k_mark<K, true>), dim3(kMarkBlocks), dim3(256), 0, s, a.work, a.n_work,
+                       (const K*)a.rkey, (const K*)a.skey, a.level - a.l_par, a.owner, a.rank,
+                       a.e4_off, a.e4_ent, a.elsewhere, a.here);
+  }
+  hipLaunchKernelGGL(k_types_deep<K>, dim3(grid_for(a.n_src)), dim3(256), 0, s, a.n_src,
+                     (const K*)a.skey, a.level, a.l_par, a.owner, a.rank, a.elsewhere, a.here,
+                     a.types);
+}
+
 void launch_types_crit(bool key64, const BoxTypeLevel& a, hipStream_t s) {
-#define FMMDS_CRIT(K)                                                                          \
-  do {                                                                                         \
-    if (a.n_recv)                                                                              \
-      hipLaunchKernelGGL(k_mark_crit<K>, dim3(grid_for(a.n_recv)), dim3(256), 0, s, a.n_recv, \
-                         a.rchild, (const K*)a.rkey_par, a.owner, a.rank, a.e4_off, a.e4_ent,  \
-                         a.flags);                                                             \
-    hipLaunchKernelGGL(k_types_crit<K>, dim3(grid_for(a.n_src)), dim3(256), 0, s, a.n_src,     \
-                       a.schild, (const K*)a.skey_par, a.owner, a.rank, a.flags, a.types);     \
-  } while (0)
-  if (key64) FMMDS_CRIT(uint64_t);
-  else FMMDS_CRIT(uint32_t);
-#undef FMMDS_CRIT
+  if (key64) types_crit<uint64_t>(a, s);
+  else types_crit<uint32_t>(a, s);
 }
 
 void launch_types_deep(bool key64, const BoxTypeLevel& a, hipStream_t s) {
-#define FMMDS_DEEP(K)                                                                          \
-  do {                                                                                         \
-    if (a.n_recv)                                                                              \
-      hipLaunchKernelGGL(k_mark_deep<K>, dim3(grid_for(a.n_recv)), dim3(256), 0, s, a.n_recv, \
-                         (const K*)a.rkey, (const K*)a.skey, a.level, a.l_par, a.owner, a.rank, \
-                         a.e4_off, a.e4_ent, a.flags);                                         \
-    hipLaunchKernelGGL(k_types_deep<K>, dim3(grid_for(a.n_src)), dim3(256), 0, s, a.n_src,     \
-                       (const K*)a.skey, a.level, a.l_par, a.owner, a.rank, a.flags, a.types); \
-  } while (0)
-  if (key64) FMMDS_DEEP(uint64_t);
-  else FMMDS_DEEP(uint32_t);
-#undef FMMDS_DEEP
+  if (key64) types_deep<uint64_t>(a, s);
+  else types_deep<uint32_t>(a, s);
 }
 
 }  // namespace fmmds

@@ -154,7 +154,10 @@ struct BoxTypeLevel {
   const uint32_t* owner;        // rank of every Morton index of l_par
   const uint32_t* e4_off;       // the level's E4 lists
   const uint32_t* e4_ent;
-  uint32_t* flags;              // n_src words, zeroed
+  uint8_t* elsewhere;           // n_src marks "needed by another rank", zeroed
+  uint8_t* here;                // n_src marks "needed by this rank", zeroed
+  uint32_t* work;               // n_recv slots: receivers that read their lists
+  uint32_t* n_work;             // their count, zeroed
   uint8_t* types;               // n_src outputs
 };
 void launch_partition(bool key64, const void* rkey, const uint32_t* rbegin, uint32_t n_boxes,

@@ -1295,11 +1295,21 @@ fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owne
   const TreeImpl* impl = (const TreeImpl*)t->impl;
   const bool key64 = t->key_bits == 64;
   const uint32_t l_crit = l_par - 1;
-  uint32_t n_max = 1;
-  for (uint32_t l = l_crit; l <= t->depth; ++l) n_max = std::max(n_max, t->src[l].n);
-  // flags are zeroed in whole 16-byte words
-  void* flags = cache_alloc(round_up((size_t)n_max, 4) * 4, st);
+  uint32_t n_max = 1, r_max = 1;
+  for (uint32_t l = l_crit; l <= t->depth; ++l) {
+    n_max = std::max(n_max, t->src[l].n);
+    r_max = std::max(r_max, t->recv[l].n);
+  }
+  // two mark arrays, the work counter and the work list, each 16-byte
+  // aligned and zeroed in whole 16-byte words
+  const size_t marks_b = round_up((size_t)n_max, 16);
+  const size_t clear_b = 2 * marks_b + 16;
+  void* flags = cache_alloc(clear_b + round_up((size_t)r_max * 4, 16), st);
   if (!flags) return FMMDS_ERR_NOMEM;
+  uint8_t* elsewhere = (uint8_t*)flags;
+  uint8_t* here = elsewhere + marks_b;
+  uint32_t* n_work = (uint32_t*)(here + marks_b);
+  uint32_t* work = n_work + 4;
   size_t at = 0;
   for (uint32_t l = 2; l <= t->depth; ++l) {
     const uint32_t ns = t->src[l].n;
@@ -1309,7 +1319,7 @@ fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owne
       launch_fill_u8(ty, ns, FMMDS_BOX_DOMESTIC, st);
       continue;
     }
-    launch_zero(flags, round_up((size_t)ns, 4) * 4, st);
+    launch_zero(flags, clear_b, st);
     BoxTypeLevel a{};
     a.level = l;
     a.l_par = l_par;
@@ -1321,7 +1331,10 @@ fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owne
     a.owner = owner;
     a.e4_off = impl->lists[l].off[1];
     a.e4_ent = impl->lists[l].ent[1];
-    a.flags = (uint32_t*)flags;
+    a.elsewhere = elsewhere;
+    a.here = here;
+    a.work = work;
+    a.n_work = n_work;
     a.types = ty;
     if (l == l_crit) {
       a.rkey_par = t->recv[l_par].key;
