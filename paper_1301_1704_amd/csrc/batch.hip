@@ -31,18 +31,28 @@ __device__ __forceinline__ uint32_t find_set(const uint64_t* __restrict__ off, u
   return lo;
 }
 
+// Each block takes one contiguous range of `chunk` points: it finds the set
+// of its first point once, and each thread then moves forward through the
+// sets (which hold at least one point each) as its points advance. About
+// 2048 blocks, so that the digit histograms are merged by few atomics.
+
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_batch_keygen(
     const P3b* __restrict__ xyz, uint32_t n, const uint64_t* __restrict__ set_off,
     uint32_t n_sets, const uint8_t* __restrict__ set_level, uint32_t L_all,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t n_pass,
-    uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
+    uint32_t* __restrict__ hist, uint32_t* __restrict__ err, uint32_t chunk) {
   __shared__ uint32_t s_hist[kMaxPasses * 256];
+  __shared__ uint32_t s_set0;
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
+  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+  const uint64_t end = min<uint64_t>(begin + chunk, n);
+  if (threadIdx.x == 0) s_set0 = find_set(set_off, n_sets, begin);
   __syncthreads();
+  uint32_t set = s_set0;
   bool bad = false;
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
-    const uint32_t set = find_set(set_off, n_sets, i);
+  for (uint64_t i = begin + threadIdx.x; i < end; i += 256) {
+    while (set_off[set + 1] <= i) ++set;
     const uint32_t L = set_level[set];
     const float scale = (float)(1u << L);
     const uint32_t qmax = (1u << L) - 1;
@@ -77,13 +87,14 @@ void launch_batch_keygen(const float* xyz, uint32_t n, const uint64_t* set_off, 
                          const uint8_t* set_level, uint32_t L_all, bool packed, uint64_t* keys,
                          uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
                          hipStream_t s) {
-  const uint32_t grid = std::min<uint32_t>(div_up(n, 256), 2048);
+  const uint32_t chunk = 256 * div_up(div_up(n, 2048), 256);
+  const uint32_t grid = div_up(n, chunk);
   if (packed)
     hipLaunchKernelGGL(k_batch_keygen<true>, dim3(grid), dim3(256), 0, s, (const P3b*)xyz, n,
-                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err);
+                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err, chunk);
   else
     hipLaunchKernelGGL(k_batch_keygen<false>, dim3(grid), dim3(256), 0, s, (const P3b*)xyz, n,
-                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err);
+                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err, chunk);
 }
 
 // first[l * (n_sets + 1) + i] = rank of set i's first box at level l: the box
