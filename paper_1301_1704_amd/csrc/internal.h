@@ -81,6 +81,14 @@ struct ListLevelArgs {
   uint32_t key_bits_up;         // bits of the level - 1 keys including the set id
   const uint32_t* n_recv_up_dev;// if set, the parent count is read here and
                                 // n_recv_up is only the capacity
+  // Fill only: with cnt2_next set, the fill also writes the E2 / E4 counts of
+  // the receiver boxes of level + 1 (what the count kernel would compute
+  // there), from the lists it builds for their parents.
+  const uint8_t* src_mask_cur;   // level source child masks
+  const uint8_t* recv_mask_cur;  // level receiver child masks
+  const uint32_t* recv_child_cur;// level receiver first children
+  uint32_t* cnt2_next;
+  uint32_t* cnt4_next;
 };
 void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint32_t* cnt4,
                        hipStream_t s);

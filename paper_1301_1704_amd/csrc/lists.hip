@@ -150,13 +150,28 @@ __global__ __launch_bounds__(256) void k_list_count(ListLevelArgs a, uint32_t* _
   }
 }
 
-template <typename KeyT, typename A>
+// NEXT: also write the counts of level + 1 (see ListLevelArgs). E2(r) for a
+// receiver child r of p is the set of U entries marked for r. An entry u
+// (child o of the parent neighbor s at offset d' from p) sits at offset
+// 2 d' + o - q from r per axis (q: r's octant); the setup stores t - 1 with
+// t = 2 d' + o + 2 (2 bits per axis: for entries of some E2(r), t is 1..4).
+// During the split the E2 lanes also copy (child mask of u, t - 1) into a
+// small per-child LDS list; afterwards the lanes of the wave take one
+// (receiver child r, octant q' of r's children) pair each and count, over
+// E2(r), the children of u adjacent to r's child q', as the count kernel
+// does one level down. The lanes stay busy in that phase, instead of
+// counting inside the split where only the E2 lanes are.
+constexpr int kE2Max = 27;
+
+template <typename KeyT, typename A, bool NEXT>
 __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32_t* __restrict__ off2,
                                                    const uint32_t* __restrict__ off4,
                                                    uint32_t* __restrict__ ent2,
                                                    uint32_t* __restrict__ ent4) {
   __shared__ uint32_t s_rank[8][kUnion];
   __shared__ uint8_t s_adj[8][kUnion];
+  __shared__ uint8_t s_off[NEXT ? 8 : 1][NEXT ? kUnion : 1];
+  __shared__ uint32_t s_e2[NEXT ? 4 : 1][NEXT ? 16 : 1][NEXT ? kE2Max : 1];
   const KeyT* __restrict__ pkey = (const KeyT*)a.recv_key_up;
   const KeyT* __restrict__ skey = (const KeyT*)a.src_key_up;
   const uint32_t lane = threadIdx.x & 63u, j = lane & 31u, h = threadIdx.x >> 5;
@@ -169,6 +184,7 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
   // upbase: batch rank of the set's first box at level - 1 (parent-level E2
   // entries are stored relative to it); base: the same at level l.
   uint32_t j0 = 0, cnt = 0, upbase = 0, base = 0, rmask = 0, rfirst = 0;
+  bool next_zero = false;  // the set has no lists at level + 1
   if (live) {
     if (a.up_all) {
       cnt = a.n_src_up;
@@ -182,25 +198,32 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
       upbase = a.first_up[set];
       if (a.up_all) cnt = a.first_up[set + 1] - upbase;
       if (a.set_level[set] < a.level) cnt = 0;  // the set's lists stop above this level
+      next_zero = a.set_level[set] < a.level + 1;
     }
     rmask = a.recv_mask_up[p];
     rfirst = a.recv_child_up[p];
   }
-  // Offsets of p's receiver children (lane j holds child j), loaded before
-  // any store: on this GPU a wait for a load also waits for earlier stores.
-  uint32_t my_o2 = 0, my_o4 = 0;
+  // Offsets of p's receiver children (lane j holds child j), and with NEXT
+  // their child masks and first children, loaded before any store: on this
+  // GPU a wait for a load also waits for earlier stores.
+  uint32_t my_o2 = 0, my_o4 = 0, my_rm = 0, my_rc = 0;
   if (j < (uint32_t)__popc(rmask)) {
     my_o2 = off2[rfirst + j];
     my_o4 = off4[rfirst + j];
+    if (NEXT) {
+      my_rm = a.recv_mask_cur[rfirst + j];
+      my_rc = a.recv_child_cur[rfirst + j];
+    }
   }
   uint32_t m = 0, cb = 0, xm0 = 0, xm1 = 0, ym0 = 0, ym1 = 0, zm0 = 0, zm1 = 0;
+  int dx = 0, dy = 0, dz = 0;
   if (j < cnt) {
     const uint32_t s = upbase + (a.up_all ? j : a.e2_ent_up[j0 + j]);
     const A sk = (A)skey[s], pk = (A)pkey[p];
     const A X = (A)kAxisX;
-    const int dx = axis_delta<A>(sk, pk, X, (A)1);
-    const int dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
-    const int dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
+    dx = axis_delta<A>(sk, pk, X, (A)1);
+    dy = axis_delta<A>(sk, pk, (A)(X << 1), (A)2);
+    dz = axis_delta<A>(sk, pk, (A)(X << 2), (A)4);
     m = a.src_mask_up[s];
     cb = a.src_child_up[s] - base;
     // Receiver octants a child with axis bit 0 / 1 is adjacent to, per axis:
@@ -228,24 +251,50 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
         U[pos + r] = cb + r;
         ADJ[pos + r] = (uint8_t)(((o & 1u) ? xm1 : xm0) & ((o & 2u) ? ym1 : ym0) &
                                  ((o & 4u) ? zm1 : zm0));
+        if (NEXT) {
+          const uint32_t tx = (uint32_t)(2 * dx + 1) + (o & 1u);
+          const uint32_t ty = (uint32_t)(2 * dy + 1) + ((o >> 1) & 1u);
+          const uint32_t tz = (uint32_t)(2 * dz + 1) + ((o >> 2) & 1u);
+          s_off[h][pos + r] = (uint8_t)((tx & 3u) | (ty & 3u) << 2 | (tz & 3u) << 4);
+        }
       }
     }
   }
   __builtin_amdgcn_wave_barrier();
-  // Split, the whole wave on one parent at a time.
+  // Both parents' U into registers; with NEXT also the child masks of the U
+  // entries (global loads, issued before any store).
+  uint32_t u[2][4], ad[2], uo[2], um[2], T[2];
 #pragma unroll
   for (uint32_t hh = 0; hh < 2; ++hh) {
-    const uint32_t T = (uint32_t)__builtin_amdgcn_readlane(total, 32 * hh);
+    T[hh] = (uint32_t)__builtin_amdgcn_readlane(total, 32 * hh);
     const uint32_t* U = s_rank[(h & ~1u) + hh];
     const uint8_t* ADJ = s_adj[(h & ~1u) + hh];
-    uint32_t u[4], ad = 0;
+    ad[hh] = uo[hh] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t idx = 64u * k + lane;
-      u[k] = idx < T ? U[idx] : 0u;
-      ad |= (idx < T ? (uint32_t)ADJ[idx] : 0u) << (8 * k);
+      u[hh][k] = idx < T[hh] ? U[idx] : 0u;
+      ad[hh] |= (idx < T[hh] ? (uint32_t)ADJ[idx] : 0u) << (8 * k);
+      if (NEXT) uo[hh] |= (idx < T[hh] ? (uint32_t)s_off[(h & ~1u) + hh][idx] : 0u) << (8 * k);
     }
-    const uint32_t n_chunks = (T + 63u) >> 6;
+  }
+  if (NEXT) {
+#pragma unroll
+    for (uint32_t hh = 0; hh < 2; ++hh) {
+      const uint32_t gbase = (uint32_t)__builtin_amdgcn_readlane(base, 32 * hh);
+      um[hh] = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (64u * k + lane < T[hh])
+          um[hh] |= (uint32_t)a.src_mask_cur[gbase + u[hh][k]] << (8 * k);
+    }
+  }
+  // Split, the whole wave on one parent at a time.
+  uint32_t my_n2 = 0;  // NEXT: lane 32 hh + i holds |E2| of child i of parent hh
+  uint32_t* E2L = NEXT ? &s_e2[threadIdx.x >> 6][0][0] : nullptr;
+#pragma unroll
+  for (uint32_t hh = 0; hh < 2; ++hh) {
+    const uint32_t n_chunks = (T[hh] + 63u) >> 6;
     uint32_t qm = (uint32_t)__builtin_amdgcn_readlane(rmask, 32 * hh), child = 32 * hh;
 #pragma unroll 1
     while (qm) {
@@ -254,23 +303,72 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
       // next free slot of each list (wave-uniform)
       uint32_t* d2 = ent2 + (uint32_t)__builtin_amdgcn_readlane(my_o2, child);
       uint32_t* d4 = ent4 + (uint32_t)__builtin_amdgcn_readlane(my_o4, child);
+      uint32_t n2r = 0;
+      uint32_t* el = NEXT ? E2L + (8 * hh + (child & 7u)) * kE2Max : nullptr;
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k) {
         if (k < n_chunks) {
-          const uint32_t rem = T - 64u * k;  // valid lanes: 0 .. rem - 1
-          const bool is2 = (ad >> (8 * k + q)) & 1u;  // 0 on invalid lanes
+          const uint32_t rem = T[hh] - 64u * k;  // valid lanes: 0 .. rem - 1
+          const bool is2 = (ad[hh] >> (8 * k + q)) & 1u;  // 0 on invalid lanes
           const uint64_t b2 = __ballot(is2);
           const uint32_t i2 = mbcnt(b2);
           // E2 lanes go to d2 in order; the other valid lanes (a prefix of
           // the wave minus the E2 lanes) go to d4 in order.
           uint32_t* dst = is2 ? d2 + i2 : d4 + (lane - i2);
-          if (lane < rem) *dst = u[k];
+          if (lane < rem) *dst = u[hh][k];
+          if (NEXT && is2)
+            el[n2r + i2] = ((um[hh] >> (8 * k)) & 0xFFu) | ((uo[hh] >> (8 * k)) & 0xFFu) << 8;
           const uint32_t n2 = (uint32_t)__popcll(b2);
           d2 += n2;
           d4 += min(rem, 64u) - n2;
+          n2r += n2;
         }
       }
+      if (NEXT && lane == child) my_n2 = n2r;
       ++child;
+    }
+  }
+  if (NEXT) {
+    __builtin_amdgcn_wave_barrier();
+    // Lane 8 i + q': receiver child i of each parent in turn, octant q' of
+    // its children.
+    const uint32_t i = lane >> 3, qq = lane & 7u;
+    const uint32_t qx = qq & 1u, qy = (qq >> 1) & 1u, qz = (qq >> 2) & 1u;
+#pragma unroll
+    for (uint32_t hh = 0; hh < 2; ++hh) {
+      const uint32_t pm = (uint32_t)__builtin_amdgcn_readlane(rmask, 32 * hh);
+      const bool nz = __builtin_amdgcn_readlane(next_zero ? 1 : 0, 32 * hh) != 0;
+      const uint32_t rm = (uint32_t)__shfl(my_rm, 32 * hh + i);
+      const uint32_t rc = (uint32_t)__shfl(my_rc, 32 * hh + i);
+      const uint32_t n2 = (uint32_t)__shfl(my_n2, 32 * hh + i);
+      if (i < (uint32_t)__popc(pm) && ((rm >> qq) & 1u)) {
+        uint32_t mm = pm;
+        for (uint32_t t = 0; t < i; ++t) mm &= mm - 1;
+        const uint32_t q = (uint32_t)__builtin_ctz(mm);  // octant of r
+        // Per axis, the children of u adjacent to r's child q' for offsets
+        // -1, 0, +1 of u from r, in bytes 0, 1, 2 (offset -1: u's children
+        // with the bit set, if q' has it clear; +1: those with it clear, if
+        // q' has it set), shifted up one byte when r's own axis bit is 1, so
+        // that byte t - 1 is the mask.
+        const uint32_t Wx = ((qx ? 0u : 0xAAu) | 0xFF00u | (qx ? 0x55u : 0u) << 16) << (8 * (q & 1u));
+        const uint32_t Wy = ((qy ? 0u : 0xCCu) | 0xFF00u | (qy ? 0x33u : 0u) << 16)
+                            << (8 * ((q >> 1) & 1u));
+        const uint32_t Wz = ((qz ? 0u : 0xF0u) | 0xFF00u | (qz ? 0x0Fu : 0u) << 16)
+                            << (8 * ((q >> 2) & 1u));
+        const uint32_t* el = E2L + (8 * hh + i) * kE2Max;
+        uint32_t c_all = 0, c2 = 0;
+        for (uint32_t e = 0; e < n2; ++e) {
+          const uint32_t v = el[e];
+          const uint32_t adj = __builtin_amdgcn_ubfe(Wx, ((v >> 8) & 3u) * 8, 8) &
+                               __builtin_amdgcn_ubfe(Wy, ((v >> 10) & 3u) * 8, 8) &
+                               __builtin_amdgcn_ubfe(Wz, ((v >> 12) & 3u) * 8, 8);
+          c_all += (uint32_t)__popc(v & 0xFFu);
+          c2 += (uint32_t)__popc(v & adj);
+        }
+        const uint32_t slot = rc + (uint32_t)__popc(rm & ((1u << qq) - 1u));
+        a.cnt2_next[slot] = nz ? 0u : c2;
+        a.cnt4_next[slot] = nz ? 0u : c_all - c2;
+      }
     }
   }
 }
@@ -291,20 +389,27 @@ void launch_list_count(bool key64, const ListLevelArgs& a, uint32_t* cnt2, uint3
                        cnt4);
 }
 
-void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
+template <bool NEXT>
+static void list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
                       const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s) {
-  if (a.n_recv_up == 0) return;
   const uint32_t grid = div_up(a.n_recv_up, 8);
   const bool narrow = a.key_bits_up <= 32;
   if (key64 && narrow)
-    hipLaunchKernelGGL((k_list_fill<uint64_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, off2,
-                       off4, ent2, ent4);
+    hipLaunchKernelGGL((k_list_fill<uint64_t, uint32_t, NEXT>), dim3(grid), dim3(256), 0, s, a,
+                       off2, off4, ent2, ent4);
   else if (key64)
-    hipLaunchKernelGGL((k_list_fill<uint64_t, uint64_t>), dim3(grid), dim3(256), 0, s, a, off2,
-                       off4, ent2, ent4);
+    hipLaunchKernelGGL((k_list_fill<uint64_t, uint64_t, NEXT>), dim3(grid), dim3(256), 0, s, a,
+                       off2, off4, ent2, ent4);
   else
-    hipLaunchKernelGGL((k_list_fill<uint32_t, uint32_t>), dim3(grid), dim3(256), 0, s, a, off2,
-                       off4, ent2, ent4);
+    hipLaunchKernelGGL((k_list_fill<uint32_t, uint32_t, NEXT>), dim3(grid), dim3(256), 0, s, a,
+                       off2, off4, ent2, ent4);
+}
+
+void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
+                      const uint32_t* off4, uint32_t* ent2, uint32_t* ent4, hipStream_t s) {
+  if (a.n_recv_up == 0) return;
+  if (a.cnt2_next) list_fill<true>(key64, a, off2, off4, ent2, ent4, s);
+  else list_fill<false>(key64, a, off2, off4, ent2, ent4, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -630,7 +630,10 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
       const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
-      P.run(K_COUNT, side + (double)nr * 8, [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
+      // level 2 only: the fill of each level writes the next level's counts
+      if (l == 2)
+        P.run(K_COUNT, side + (double)nr * 8,
+              [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
       LB.off[0] = impl->outs.get<uint32_t>((size_t)nr + 1);
       LB.off[1] = impl->outs.get<uint32_t>((size_t)nr + 1);
       {
@@ -648,9 +651,17 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         LB.total[k] = hm->list_total[k][l];
         LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
       }
-      P.run(K_FILL, side + (double)nr * 8 + 4.0 * (double)(LB.total[0] + LB.total[1]), [&] {
-        launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st);
-      });
+      double next_b = 0.0;  // level + 1 counts: masks and first children in, two counts out
+      if (l < D) {
+        a.src_mask_cur = sets[0].lv[l].mask;
+        a.recv_mask_cur = sets[rs].lv[l].mask;
+        a.recv_child_cur = sets[rs].lv[l].child;
+        a.cnt2_next = cnt;
+        a.cnt4_next = cnt + round_up(nb[rs][l + 1], 4);
+        next_b = (double)nr * 5 + (double)nb[0][l] + (double)nb[rs][l + 1] * 8;
+      }
+      P.run(K_FILL, side + (double)nr * 8 + 4.0 * (double)(LB.total[0] + LB.total[1]) + next_b,
+            [&] { launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st); });
       impl->n_recv_boxes[l] = nr;
     }
 
@@ -878,7 +889,7 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
     a.key_bits_up = B.setbits + 3 * (l - 1);
     uint32_t* c2 = B.cnt;
     uint32_t* c4 = B.cnt + round_up(B.cap[l], 4);
-    P.run(K_COUNT, 0.0, [&] { launch_list_count(true, a, c2, c4, st); });
+    if (l == 2) P.run(K_COUNT, 0.0, [&] { launch_list_count(true, a, c2, c4, st); });
     {
       uint64_t* st2 = sa.take_words(scan_tiles(B.cap[l]));
       uint64_t* st4 = sa.take_words(scan_tiles(B.cap[l]));
@@ -888,6 +899,13 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
                             &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st,
                             &meta->n_boxes[0][l]);
       });
+    }
+    if (l < L) {  // the next level's counts (batch ranks; sets ending at l get zeros)
+      a.src_mask_cur = B.g[l].mask;
+      a.recv_mask_cur = B.g[l].mask;
+      a.recv_child_cur = B.g[l].child;
+      a.cnt2_next = B.cnt;
+      a.cnt4_next = B.cnt + round_up(B.cap[l + 1], 4);
     }
     P.run(K_FILL, 0.0, [&] {
       launch_list_fill(true, a, B.goff[l][0], B.goff[l][1], B.ent[l][0], B.ent[l][1], st);
