@@ -78,8 +78,8 @@ KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_coun
                  "sort_pass": "sort.hip", "keygen": "sort.hip", "digit_offsets": "sort.hip",
                  "zero": "sort.hip", "leaf": "tables.hip", "level": "tables.hip",
                  "max_occupancy": "tables.hip"}
-COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-profile "
-                "--copy-calibration")
+COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-rebuild "
+                "--no-profile --copy-calibration")
 
 
 def _kernel_class(name: str):
@@ -154,7 +154,7 @@ def kernel_stats_summary(stats_csv: str, out: str, workload_name: str):
     rows = list(csv.DictReader(open(stats_csv)))
     cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
            "-d <dir> -o run -- python3 <repo>/bench.py --workload " + workload_name +
-           " --no-cpu-baseline --no-batch --no-serving")
+           " --no-cpu-baseline --no-batch --no-serving --no-rebuild")
     lines = [f"# Kernel times (rocprofv3 --kernel-trace --stats), workload `{workload_name}`", "",
              "```", cmd, f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
              f"{os.path.relpath(out, ROOT)} --workload {workload_name}", "```", "",
@@ -314,6 +314,66 @@ def bench_near_field(F, torch, src, recv, kw, reps=5):
     return res
 
 
+def bench_rebuild(F, torch, c, kw, reps=5, sigma=1e-4):
+    """Rebuild after one time step: the benchmark's points moved by
+    sigma * N(0, 1) per coordinate (sigma 1e-4, ~2.6% of the level-8 box
+    edge), rebuilt from the previous tree in both input orders, against a
+    fresh build of the same moved points."""
+    from paper_1301_1704_amd import inputs as I
+    src2 = I.moved_points(c["src"], 250, sigma)
+    recv2 = None if c["recv"] is None else I.moved_points(c["recv"], 251, sigma)
+    L = c["max_level"]
+    moved = 0
+    for a, b in ((c["src"], src2), (c["recv"], recv2)):
+        if a is not None:
+            sc = np.float32(1 << L)
+            moved += int(np.any(np.floor(a * sc) != np.floor(b * sc), axis=1).sum())
+    n_pts = c["src"].shape[0] + (0 if recv2 is None else recv2.shape[0])
+    g_src, g_recv = torch.from_numpy(c["src"]).cuda(), None
+    if c["recv"] is not None:
+        g_recv = torch.from_numpy(c["recv"]).cuda()
+    prev = F.build(g_src, g_recv, **kw)
+    m_src = torch.from_numpy(src2).cuda()
+    m_recv = None if recv2 is None else torch.from_numpy(recv2).cuda()
+    perm0 = torch.from_numpy(prev.host_perm(0).astype(np.int64)).cuda()
+    p_src = m_src[perm0].contiguous()
+    p_recv = None
+    if m_recv is not None:
+        p_recv = m_recv[torch.from_numpy(prev.host_perm(1).astype(np.int64)).cuda()].contiguous()
+
+    def timed(fn):
+        fn().free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn().free()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    rk = dict(key_bits=kw["key_bits"], cluster_s=kw["cluster_s"])
+    fresh = timed(lambda: F.build(m_src, m_recv, **kw))
+    orig = timed(lambda: F.rebuild(prev, m_src, m_recv, **rk))
+    pord = timed(lambda: F.rebuild(prev, p_src, p_recv, in_prev_order=True, **rk))
+    F.profile_reset()
+    F.profile_enable(True)
+    F.rebuild(prev, p_src, p_recv, in_prev_order=True, **rk).free()
+    torch.cuda.synchronize()
+    F.profile_enable(False)
+    br = F.profile_read()
+    prev.free()
+    res = {"workload": f"the benchmark points after one step, sigma {sigma:g} per coordinate",
+           "moved_fraction": moved / n_pts, "fresh_build_ms": fresh,
+           "rebuild_ms_original_order": orig, "rebuild_ms_prev_order": pord,
+           "points_per_s_prev_order": n_pts / (pord * 1e-3),
+           "speedup_prev_order": fresh / pord, "speedup_original_order": fresh / orig,
+           "kernels_prev_order": {k: {"launches": v["launches"],
+                                      "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2)}
+                                  for k, v in br.items()}}
+    log(f"rebuild: fresh {fresh:.3f} ms, from prev (original order) {orig:.3f} ms, "
+        f"(prev order) {pord:.3f} ms, {moved / n_pts:.2%} of points changed box")
+    return res
+
+
 def bench_serving(F, torch, args):
     """Continuous-batching serving of rebuild requests from 64 moving particle
     systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
@@ -372,6 +432,8 @@ def main():
                     help="skip the near-field sum measurement")
     ap.add_argument("--no-box-types", action="store_true",
                     help="skip the partition / source box type measurement")
+    ap.add_argument("--no-rebuild", action="store_true",
+                    help="skip the incremental rebuild measurement")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -493,6 +555,8 @@ def main():
         line["near_field"] = bench_near_field(F, torch, src, recv, kw)
     if not args.no_box_types and args.workload != "small":
         line["box_types"] = bench_box_types(F, torch, src, recv, kw)
+    if not args.no_rebuild:
+        line["rebuild"] = bench_rebuild(F, torch, c, kw)
     if not args.no_batch:
         line["batched"] = bench_batched(F, torch, args)
     if not args.no_serving:

@@ -124,6 +124,33 @@ fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv
                          uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
 
 /*
+ * Rebuild after the points moved (the dynamic problems of Section 1, where
+ * the structures are rebuilt every time step), reusing the order of a
+ * previous tree: only points whose finest-level box changed are sorted, and
+ * merged with the others, which are still in order. The result is exactly
+ * the tree fmmds_build would return for the same positions and options.
+ *   prev:     host; a tree from fmmds_build, fmmds_rebuild or a batch, with
+ *             the point counts of this build; read only, and may be freed
+ *             once this call returns.
+ *   src_xyz:  device, 3 * prev->n_src FP32 values. With in_prev_order == 0,
+ *             row j is original point j (as for fmmds_build); with 1, row k
+ *             is the point at prev's sorted position k, i.e. original point
+ *             prev->src_perm[k] (e.g. prev->src_sorted_xyz after moving).
+ *   recv_xyz: device, 3 * prev->n_recv values in the same order convention,
+ *             or NULL iff prev->shared.
+ *   opt:      host; max_level must equal prev->max_level (the sort key);
+ *             key_bits, cluster_s, stream and allocator are free.
+ *   out:      host; receives a new tree owned by the library. The output
+ *             permutations map to original indices in both conventions.
+ * FMMDS_ERR_ARG for a NULL argument, in_prev_order > 1, a recv_xyz that does
+ * not match prev->shared, or another max_level; otherwise the errors of
+ * fmmds_build. When the key and index bits together exceed 64 (deep levels
+ * with many points) the points are fully sorted instead, with the same result.
+ */
+fmmds_status fmmds_rebuild(const fmmds_tree* prev, const float* src_xyz, const float* recv_xyz,
+                           uint32_t in_prev_order, const fmmds_options* opt, fmmds_tree** out);
+
+/*
  * E2 neighbor list of every nonempty receiver box at `level` in [2, depth]
  * (Section 2.2, NeighborBookmark / NeighborList), as CSR:
  *   *offsets: device, *n_recv_boxes + 1 entries; box j's list is

@@ -74,6 +74,9 @@ def _lib():
         L.fmmds_build.argtypes = [_vp, _u32, _vp, _u32, C.POINTER(Options),
                                   C.POINTER(C.POINTER(TreeStruct))]
         L.fmmds_build.restype = C.c_int
+        L.fmmds_rebuild.argtypes = [C.POINTER(TreeStruct), _vp, _vp, _u32, C.POINTER(Options),
+                                    C.POINTER(C.POINTER(TreeStruct))]
+        L.fmmds_rebuild.restype = C.c_int
         for f in ("fmmds_neighbors", "fmmds_interactions"):
             getattr(L, f).argtypes = [C.POINTER(TreeStruct), _u32, C.POINTER(_vp), C.POINTER(_vp),
                                       C.POINTER(_u32), C.POINTER(_u64)]
@@ -130,7 +133,7 @@ def exported_symbols():
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
             "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types",
-            "fmmds_near_field"]
+            "fmmds_near_field", "fmmds_rebuild"]
 
 
 class DisplaceSet(C.Structure):
@@ -389,16 +392,8 @@ class Tree:
         return out
 
 
-def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int = 0,
-          stream=None, allocator: str = "pool") -> Tree:
-    """Build the FMM data structures on the GPU.
-
-    src, recv: torch float32 CUDA tensors of shape (n, 3), contiguous; recv
-    None means receivers are the sources. stream: a torch.cuda.Stream (default:
-    the current stream). allocator: "pool" (the library's stream-ordered pool)
-    or "torch" (torch's caching allocator)."""
+def _build_options(src, recv, max_level, key_bits, cluster_s, stream, allocator):
     import torch
-    L = _lib()
     for name, x in (("src", src), ("recv", recv)):
         if x is None:
             continue
@@ -418,12 +413,48 @@ def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int 
         opt.alloc, opt.release = keep.alloc, keep.release
     elif allocator != "pool":
         raise ValueError(allocator)
+    return opt, keep
+
+
+def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int = 0,
+          stream=None, allocator: str = "pool") -> Tree:
+    """Build the FMM data structures on the GPU.
+
+    src, recv: torch float32 CUDA tensors of shape (n, 3), contiguous; recv
+    None means receivers are the sources. stream: a torch.cuda.Stream (default:
+    the current stream). allocator: "pool" (the library's stream-ordered pool)
+    or "torch" (torch's caching allocator)."""
+    L = _lib()
+    opt, keep = _build_options(src, recv, max_level, key_bits, cluster_s, stream, allocator)
     out = C.POINTER(TreeStruct)()
     st = L.fmmds_build(src.data_ptr(), src.shape[0],
                        None if recv is None else recv.data_ptr(),
                        0 if recv is None else recv.shape[0], C.byref(opt), C.byref(out))
     if st != OK:
         raise FmmdsError(st, "fmmds_build")
+    return Tree(out, keep)
+
+
+def rebuild(prev: Tree, src, recv=None, *, in_prev_order: bool = False, key_bits: int = None,
+            cluster_s: int = 0, stream=None, allocator: str = "pool") -> Tree:
+    """Rebuild for moved points (fmmds_rebuild): the result equals
+    build(src, recv, max_level=prev.max_level, ...) on the same positions,
+    computed from prev's order (only points that changed finest box are
+    sorted). in_prev_order: src / recv hold the positions in prev's sorted
+    order (row k is original point prev's perm[k]) instead of original order."""
+    L = _lib()
+    if prev._h is None:
+        raise ValueError("prev is freed")
+    kb = prev.key_bits if key_bits is None else key_bits
+    opt, keep = _build_options(src, recv, prev.max_level, kb, cluster_s, stream, allocator)
+    if src.shape[0] != prev.n_src or (recv is None) != prev.shared or (
+            recv is not None and recv.shape[0] != prev.n_recv):
+        raise ValueError("point counts (or shared receivers) differ from prev")
+    out = C.POINTER(TreeStruct)()
+    st = L.fmmds_rebuild(prev._h, src.data_ptr(), None if recv is None else recv.data_ptr(),
+                         1 if in_prev_order else 0, C.byref(opt), C.byref(out))
+    if st != OK:
+        raise FmmdsError(st, "fmmds_rebuild")
     return Tree(out, keep)
 
 

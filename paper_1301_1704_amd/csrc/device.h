@@ -40,6 +40,23 @@ __device__ __forceinline__ uint32_t spread3_10(uint32_t x) {
   return x;
 }
 
+// Box of a point at level L (1 <= L <= 21): floor(x * 2^L) per axis in FP32
+// (the scaling is exact), interleaved. `ok` is false for a coordinate
+// outside [0, 1) or NaN; such a point gets box 0.
+__device__ __forceinline__ uint64_t point_key(float x, float y, float z, uint32_t L, bool& ok) {
+  const float scale = (float)(1u << L);
+  const uint32_t qmax = (1u << L) - 1;
+  ok = (x >= 0.0f && x < 1.0f) && (y >= 0.0f && y < 1.0f) && (z >= 0.0f && z < 1.0f);
+  uint32_t qx = 0, qy = 0, qz = 0;
+  if (ok) {
+    qx = min((uint32_t)floorf(x * scale), qmax);
+    qy = min((uint32_t)floorf(y * scale), qmax);
+    qz = min((uint32_t)floorf(z * scale), qmax);
+  }
+  if (L <= 10) return spread3_10(qx) | (spread3_10(qy) << 1) | (spread3_10(qz) << 2);
+  return spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+}
+
 // ---------------------------------------------------------------------------
 // Wave64 primitives.
 // ---------------------------------------------------------------------------
@@ -148,6 +165,28 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* status, uint32_t til
   }
   if (lane == 0) st_status(status + tile, kStInc | (excl + agg));
   return excl;
+}
+
+// Chain per-(item, wave) flag counts of a compaction tile across tiles. The
+// NSLOT (<= 64) counts sit in s_cnt in element order; on return they hold
+// exclusive prefixes within the tile and the result is the tile's exclusive
+// prefix over all earlier tiles. Called by every thread of the block.
+template <int NSLOT>
+__device__ __forceinline__ uint64_t tile_flags_prefix(uint32_t* s_cnt, uint64_t* s_excl,
+                                                      uint64_t* status, uint32_t tile) {
+  static_assert(NSLOT <= 64, "one wave scans the slots");
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t c = lane < NSLOT ? s_cnt[lane] : 0;
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane < NSLOT) s_cnt[lane] = inc - c;
+    const uint32_t total = __shfl(inc, 63, 64);
+    const uint64_t ex = lookback_wave(status, tile, total);
+    if (lane == 0) *s_excl = ex;
+  }
+  __syncthreads();
+  return *s_excl;
 }
 
 }  // namespace fmmds

@@ -26,6 +26,7 @@ struct DevMeta {
   uint32_t n_boxes[2][kMaxLevel + 1];
   uint32_t max_occ[2][kMaxLevel + 1];
   uint64_t list_total[2][kMaxLevel + 1];  // [0] = E2, [1] = E4
+  uint32_t inc_counts[2][2];              // incremental rebuild: stayers, movers per set
 };
 
 // Sort elements: with `packed`, one uint64 holding (key << 32 | index) for keys
@@ -43,7 +44,8 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 uint32_t sort_tiles(uint32_t n, int items);
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
-                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items);
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
+                      const uint32_t* n_dev = nullptr);  // n_dev: count on the device, n = capacity
 
 // ---- tables.hip
 void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
@@ -99,6 +101,20 @@ void launch_scan_counts2(const uint32_t* cnt2, const uint32_t* cnt4, uint32_t n,
                          uint32_t* off4, uint64_t* total2, uint64_t* total4, uint32_t* overflow,
                          uint64_t* status2, uint64_t* status4, uint32_t* tile_counter,
                          hipStream_t s, const uint32_t* n_dev = nullptr);
+
+// ---- rebuild.hip
+void launch_inc_classify(const float* xyz, bool prev_order, const float* old_xyz,
+                         const uint32_t* old_perm, uint32_t n, uint32_t L, uint32_t ib,
+                         uint32_t n_pass, uint64_t* st_v, uint32_t* st_slot, uint64_t* mv_v,
+                         uint32_t* mv_slot, uint32_t* hist, uint32_t* err, uint64_t* status,
+                         uint32_t* tile_counter, uint32_t* counts, float* staged,
+                         hipStream_t s);  // staged: 3 n floats, written unless prev_order
+void launch_inc_scatter(const float* xyz, const uint32_t* old_perm, uint32_t n, float* out,
+                        hipStream_t s);
+void launch_inc_merge(bool packed, const uint64_t* st_v, const uint32_t* st_slot, uint32_t ns,
+                      const uint64_t* mv_v, const uint32_t* mv_slot, uint32_t nm,
+                      const float* xyz, uint32_t ib, uint64_t* sk, uint32_t* sv,
+                      float* sorted_xyz, hipStream_t s);  // xyz indexed by slot
 
 // ---- batch.hip kernels
 struct LevelPtrs {

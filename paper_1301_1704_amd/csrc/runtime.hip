@@ -323,12 +323,13 @@ void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 enum KernelClass {
   K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
-  K_REBASE, K_NCLASS
+  K_REBASE, K_CLASSIFY, K_PLACE, K_NCLASS
 };
 const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
                                           "sort_pass", "leaf",        "level",
                                           "max_occupancy", "list_count", "scan_counts",
-                                          "list_fill",     "batch_rebase"};
+                                          "list_fill",     "batch_rebase", "inc_classify",
+                                          "inc_place"};
 
 struct ClassStat {
   uint64_t launches = 0;
@@ -406,8 +407,14 @@ struct Prof {
   }
 };
 
+// Index bits of the incremental merge value for n points.
+uint32_t index_bits(uint32_t n) { return n <= 2 ? 1u : 32u - (uint32_t)__builtin_clz(n - 1); }
+
+// prev: with a previous tree, the order is rebuilt incrementally from it
+// (prev_order: the coordinates are given in prev's sorted order).
 fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, uint32_t n_recv,
-                   const fmmds_options* opt, fmmds_tree** out) {
+                   const fmmds_options* opt, fmmds_tree** out,
+                   const fmmds_tree* prev = nullptr, bool prev_order = false) {
   const bool shared = recv_xyz == nullptr;
   if (shared) n_recv = n_src;
   if (!src_xyz || !opt || n_src == 0 || n_recv == 0 || n_src >= 0xFFFFFFFFu ||
@@ -454,13 +461,29 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     sets[1].xyz = shared ? src_xyz : recv_xyz;
     sets[1].n = n_recv;
 
+    // Incremental order per set: the merge value (key, index) must fit 64 bits.
+    bool inc[2] = {false, false};
+    uint32_t ibits[2] = {0, 0}, inc_pass[2] = {0, 0};
+    for (int s = 0; s < nsets; ++s) {
+      ibits[s] = index_bits(sets[s].n);
+      inc[s] = prev != nullptr && 3 * L + ibits[s] <= 64;
+      inc_pass[s] = div_up(3 * L + ibits[s], 8);
+    }
+    if (prev) {
+      sets[0].perm = const_cast<uint32_t*>(prev->src_perm);
+      sets[0].sorted_xyz = const_cast<float*>(prev->src_sorted_xyz);
+      sets[1].perm = const_cast<uint32_t*>(prev->recv_perm);
+      sets[1].sorted_xyz = const_cast<float*>(prev->recv_sorted_xyz);
+    }
+
     // ---- workspace: metadata, histograms, digit offsets, status words
     size_t words = 0, tickets = 0;
     for (int s = 0; s < nsets; ++s) {
       const uint32_t n = sets[s].n;
-      words += (size_t)n_pass * sort_tiles(n, kSortItemsDefault) * 256 + div_up(n, kCompTile);
+      const uint32_t np = inc[s] ? inc_pass[s] : n_pass;
+      words += (size_t)np * sort_tiles(n, kSortItemsDefault) * 256 + 2 * div_up(n, kCompTile);
       for (uint32_t l = 0; l < L; ++l) words += div_up(level_cap(n, l + 1), kCompTile);
-      tickets += n_pass + 1 + L;
+      tickets += np + 2 + L;
     }
     const size_t meta_b = round_up(sizeof(DevMeta), 256);
     const size_t hist_b = round_up(2 * kMaxPasses * 256 * 4, 256);
@@ -480,9 +503,59 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     SortBufs sb{};
     sb.k[0] = temps.get<uint64_t>(n_max);
     sb.k[1] = temps.get<uint64_t>(n_max);
-    if (!packed) {
+    if (!packed || prev) {
       sb.v[0] = temps.get<uint32_t>(n_max);
       sb.v[1] = temps.get<uint32_t>(n_max);
+    }
+    // incremental: stayer list, and the sorted pairs the merge writes
+    uint64_t *inc_sv[2] = {nullptr, nullptr}, *inc_fk = nullptr;
+    uint32_t *inc_ss[2] = {nullptr, nullptr}, *inc_fv = nullptr;
+    if (prev) {
+      inc_sv[0] = inc_sv[1] = temps.get<uint64_t>(n_max);
+      inc_ss[0] = inc_ss[1] = temps.get<uint32_t>(n_max);
+      inc_fk = temps.get<uint64_t>(n_max);
+      inc_fv = temps.get<uint32_t>(n_max);
+    }
+
+    // Incremental: classify every set first, then one sync for the counts,
+    // so that the movers' sort and the merge launch grids of their size.
+    const uint32_t* old_perm[2] = {sets[0].perm, sets[1].perm};  // previous tree
+    const float* old_xyz[2] = {sets[0].sorted_xyz, sets[1].sorted_xyz};
+    uint64_t* inc_mv[2] = {sb.k[0], sb.k[0]};
+    uint32_t* inc_ms[2] = {sb.v[0], sb.v[0]};
+    uint32_t n_stay[2] = {0, 0}, n_move[2] = {0, 0};
+    float* staged[2] = {nullptr, nullptr};  // original-order positions, gathered in slot order
+    if (prev) {
+      bool any = false;
+      for (int s = 0; s < nsets; ++s) {
+        if (!inc[s]) continue;
+        any = true;
+        const uint32_t n = sets[s].n;
+        if (s == 1) {  // set 0's buffers are still in use
+          inc_mv[1] = temps.get<uint64_t>(n);
+          inc_ms[1] = temps.get<uint32_t>(n);
+          inc_sv[1] = temps.get<uint64_t>(n);
+          inc_ss[1] = temps.get<uint32_t>(n);
+        }
+        if (!prev_order) staged[s] = temps.get<float>(3 * (size_t)n);
+        uint64_t* stw = sa.take_words(div_up(n, kCompTile));
+        uint32_t* tk = sa.take_ticket();
+        P.run(K_CLASSIFY, (double)n * (4 + 12 + 12 + 12 + (prev_order ? 0 : 12)), [&] {
+          launch_inc_classify(sets[s].xyz, prev_order, old_xyz[s], old_perm[s], n, L, ibits[s],
+                              inc_pass[s], inc_sv[s], inc_ss[s], inc_mv[s], inc_ms[s],
+                              hist + s * kMaxPasses * 256, &meta->err_range, stw, tk,
+                              meta->inc_counts[s], staged[s], st);
+        });
+      }
+      if (any) {
+        DevMeta* hm = host_meta();
+        fetch_meta(meta, hm, st);
+        if (hm->err_range) throw Fail{FMMDS_ERR_RANGE};
+        for (int s = 0; s < nsets; ++s) {
+          n_stay[s] = hm->inc_counts[s][0];
+          n_move[s] = hm->inc_counts[s][1];
+        }
+      }
     }
 
     for (int s = 0; s < nsets; ++s) {
@@ -522,21 +595,59 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       // ---- keys and sort
       uint32_t* h = hist + s * kMaxPasses * 256;
       uint32_t* g = goff + s * kMaxPasses * 256;
-      P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
-        launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
-      });
-      P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
-      for (uint32_t p = 0; p < n_pass; ++p) {
-        const int a = p & 1, b = a ^ 1;
-        const uint32_t shift = (packed ? 32 : 0) + 8 * p;
-        uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
-        uint32_t* tk = sa.take_ticket();
-        P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
-          launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256, stw,
-                           tk, st, kSortItemsDefault);
+      const uint64_t* fin_k = nullptr;
+      const uint32_t* fin_v = nullptr;
+      const float* leaf_xyz = S.xyz;  // null: the merge already wrote the coordinates
+      if (inc[s]) {
+        // The movers sorted by (key, index), then merged with the stayers.
+        const uint32_t ib = ibits[s], np = inc_pass[s], nm = n_move[s];
+        uint64_t* mk[2] = {inc_mv[s], s == 0 ? sb.k[1] : temps.get<uint64_t>(n)};
+        uint32_t* mv[2] = {inc_ms[s], s == 0 ? sb.v[1] : temps.get<uint32_t>(n)};
+        P.run(K_DIGITS, (double)np * 2048, [&] { launch_digit_offsets(h, g, np, st); });
+        for (uint32_t p = 0; p < np && nm > 0; ++p) {
+          const int a = p & 1, b = a ^ 1;
+          uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
+          uint32_t* tk = sa.take_ticket();
+          P.run(K_SORT, (double)nm * 24, [&] {
+            launch_sort_pass(false, mk[a], mk[b], mv[a], mv[b], nm, 8 * p, g + p * 256, stw, tk,
+                             st, kSortItemsDefault);
+          });
+        }
+        const int mf = nm > 0 ? (int)(np & 1) : 0;
+        P.run(K_PLACE, (double)n * (8 + 4 + 12 + 8 + (packed ? 0 : 4) + 12), [&] {
+          launch_inc_merge(packed, inc_sv[s], inc_ss[s], n_stay[s], mk[mf], mv[mf], nm,
+                           prev_order ? S.xyz : staged[s], ib, inc_fk, inc_fv, S.sorted_xyz,
+                           st);
         });
+        fin_k = inc_fk;
+        fin_v = inc_fv;
+        leaf_xyz = nullptr;
+      } else {
+        if (prev && prev_order) {
+          // the merge value does not fit: full sort, from original order
+          float* x = temps.get<float>(3 * (size_t)n);
+          P.run(K_PLACE, 0.0, [&] { launch_inc_scatter(S.xyz, old_perm[s], n, x, st); });
+          S.xyz = x;
+          leaf_xyz = x;
+        }
+        P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
+          launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
+        });
+        P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+        for (uint32_t p = 0; p < n_pass; ++p) {
+          const int a = p & 1, b = a ^ 1;
+          const uint32_t shift = (packed ? 32 : 0) + 8 * p;
+          uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
+          uint32_t* tk = sa.take_ticket();
+          P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
+            launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,
+                             stw, tk, st, kSortItemsDefault);
+          });
+        }
+        const int fin = n_pass & 1;
+        fin_k = sb.k[fin];
+        fin_v = sb.v[fin];
       }
-      const int fin = n_pass & 1;
 
       // ---- leaf level, then coarser levels
       {
@@ -544,10 +655,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         uint32_t* tk = sa.take_ticket();
         // sorted pairs in, permutation + gathered and written coordinates out;
         // leaf keys and bookmarks are added once the box count is known
-        P.run(K_LEAF, (double)n * ((packed ? 8 : 12) + 4 + 12 + 12), [&] {
-          launch_leaf(packed, key64, sb.k[fin], sb.v[fin], S.xyz, n, S.perm,
-                      S.sorted_xyz, S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L],
-                      st);
+        P.run(K_LEAF, (double)n * ((packed ? 8 : 12) + 4 + (leaf_xyz ? 12 + 12 : 0)), [&] {
+          launch_leaf(packed, key64, fin_k, fin_v, leaf_xyz, n, S.perm, S.sorted_xyz,
+                      S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L], st);
         }, s, (int)L);
       }
       for (int l = (int)L - 1; l >= 0; --l) {
@@ -1393,6 +1503,19 @@ fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv
   if (!out) return FMMDS_ERR_ARG;
   *out = nullptr;
   return fmmds::build(src_xyz, n_src, recv_xyz, n_recv, opt, out);
+}
+
+fmmds_status fmmds_rebuild(const fmmds_tree* prev, const float* src_xyz, const float* recv_xyz,
+                           uint32_t in_prev_order, const fmmds_options* opt, fmmds_tree** out) {
+  if (!out) return FMMDS_ERR_ARG;
+  *out = nullptr;
+  if (!prev || !opt || in_prev_order > 1) return FMMDS_ERR_ARG;
+  if ((recv_xyz == nullptr) != (prev->shared != 0)) return FMMDS_ERR_ARG;
+  if (opt->max_level != prev->max_level) return FMMDS_ERR_ARG;
+  if (!prev->src_perm || !prev->src_sorted_xyz || !prev->recv_perm || !prev->recv_sorted_xyz)
+    return FMMDS_ERR_ARG;
+  return fmmds::build(src_xyz, prev->n_src, recv_xyz, prev->n_recv, opt, out, prev,
+                      in_prev_order != 0);
 }
 
 fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,

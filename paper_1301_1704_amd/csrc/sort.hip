@@ -49,26 +49,15 @@ __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint
   __shared__ uint32_t s_hist[kMaxPasses * 256];
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
   __syncthreads();
-  const float scale = (float)(1u << L);
-  const uint32_t qmax = (1u << L) - 1;
   bool bad = false;
   for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
     const P3 p = xyz[i];
-    const bool ok = (p.x >= 0.0f && p.x < 1.0f) && (p.y >= 0.0f && p.y < 1.0f) &&
-                    (p.z >= 0.0f && p.z < 1.0f);
+    bool ok;
+    const uint64_t key = point_key(p.x, p.y, p.z, L, ok);
     bad |= !ok;
-    uint32_t qx = 0, qy = 0, qz = 0;
-    if (ok) {
-      qx = min((uint32_t)floorf(p.x * scale), qmax);
-      qy = min((uint32_t)floorf(p.y * scale), qmax);
-      qz = min((uint32_t)floorf(p.z * scale), qmax);
-    }
-    uint64_t key;
     if (PACKED) {
-      key = spread3_10(qx) | (spread3_10(qy) << 1) | (spread3_10(qz) << 2);
       keys[i] = (key << 32) | (uint32_t)i;
     } else {
-      key = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
       keys[i] = key;
       vals[i] = (uint32_t)i;
     }
@@ -128,8 +117,9 @@ constexpr int kSortWaves = kSortBlock / 64;
 template <bool PACKED, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ vout, uint32_t n, uint32_t shift, const uint32_t* __restrict__ goff,
-    uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter) {
+    uint32_t* __restrict__ vout, uint32_t n_host, uint32_t shift, const uint32_t* __restrict__ goff,
+    uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
+    const uint32_t* __restrict__ n_dev) {
   constexpr int TILE = kSortBlock * ITEMS;
   constexpr int WSEG = 64 * ITEMS;
   __shared__ uint64_t s_key[TILE];
@@ -141,10 +131,14 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   __shared__ uint32_t s_tile;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   for (uint32_t i = tid; i < kSortWaves * 256; i += kSortBlock) (&s_hist[0][0])[i] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
+  // With the count on the device the grid covers the capacity; tiles past
+  // the count exit (tiles only look back at lower tile ids).
+  if ((uint64_t)tile * TILE >= n && tile > 0) return;
   const uint64_t wbase = (uint64_t)tile * TILE + (uint64_t)w * WSEG;
 
   uint64_t k[ITEMS];
@@ -221,11 +215,12 @@ uint32_t sort_tiles(uint32_t n, int items) { return div_up(n, (uint64_t)kSortBlo
 
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
-                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items) {
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
+                      const uint32_t* n_dev) {
   const uint32_t grid = sort_tiles(n, items);
 #define FMMDS_SORT(P, I)                                                                        \
   hipLaunchKernelGGL((k_sort_pass<P, I>), dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin,  \
-                     vout, n, shift, goff, status, tile_counter)
+                     vout, n, shift, goff, status, tile_counter, n_dev)
   if (items == 8) {
     if (packed) FMMDS_SORT(true, 8);
     else FMMDS_SORT(false, 8);

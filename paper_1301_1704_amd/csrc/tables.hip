@@ -19,25 +19,6 @@ struct P3 {
   float x, y, z;
 };
 
-// Chain the per-(item, wave) flag counts of a tile (in element order) across
-// tiles. On return s_cnt holds exclusive prefixes within the tile and the
-// result is the tile's exclusive prefix over all earlier tiles.
-__device__ __forceinline__ uint64_t tile_flags_prefix(uint32_t* s_cnt, uint64_t* s_excl,
-                                                      uint64_t* status, uint32_t tile) {
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const uint32_t lane = threadIdx.x;
-    const uint32_t c = lane < kCompItems * kCompWaves ? s_cnt[lane] : 0;
-    const uint32_t inc = wave_incl_scan(c);
-    if (lane < kCompItems * kCompWaves) s_cnt[lane] = inc - c;
-    const uint32_t total = __shfl(inc, 63, 64);
-    const uint64_t ex = lookback_wave(status, tile, total);
-    if (lane == 0) *s_excl = ex;
-  }
-  __syncthreads();
-  return *s_excl;
-}
-
 // ---------------------------------------------------------------------------
 // K3 + K4: from the sorted (key, index) pairs write the permutation and the
 // reordered coordinates (Algorithm 5, steps 3 and 6: SortedSrc / SortedRecv
@@ -78,7 +59,7 @@ __global__ __launch_bounds__(kCompBlock) void k_leaf(
       idx = PACKED ? (uint32_t)el : sv[e];
       if (e > 0) kp = PACKED ? (sk[e - 1] >> 32) : sk[e - 1];
       perm[e] = set_off ? idx - (uint32_t)set_off[kk >> set_shift] : idx;
-      sorted_xyz[e] = xyz[idx];
+      if (xyz) sorted_xyz[e] = xyz[idx];  // null: the coordinates are already in place
     }
     const bool f = valid && (e == 0 || kk != kp);
     const uint64_t ball = __ballot(f);
@@ -87,7 +68,7 @@ __global__ __launch_bounds__(kCompBlock) void k_leaf(
     key[i] = kk;
     if ((tid & 63) == 0) s_cnt[i * kCompWaves + w] = (uint32_t)__popcll(ball);
   }
-  const uint64_t texcl = tile_flags_prefix(s_cnt, &s_excl, status, tile);
+  const uint64_t texcl = tile_flags_prefix<kCompItems * kCompWaves>(s_cnt, &s_excl, status, tile);
 #pragma unroll
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t e = tbase + (uint64_t)i * kCompBlock + tid;
@@ -194,7 +175,7 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
     }
     cmask[i] = m;
   }
-  const uint64_t texcl = tile_flags_prefix(s_cnt, &s_excl, status, tile);
+  const uint64_t texcl = tile_flags_prefix<kCompItems * kCompWaves>(s_cnt, &s_excl, status, tile);
 #pragma unroll
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;

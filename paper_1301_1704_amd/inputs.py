@@ -37,6 +37,7 @@ TAG_SIZES = 0x06
 TAG_STEP = 0x07
 TAG_ARRIVAL = 0x08
 TAG_PICK = 0x09
+TAG_MOVE = 0x0A
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
@@ -137,6 +138,14 @@ def sphere_cluster_points(seed: int, geometry_seed: int, n: int) -> np.ndarray:
     c = cluster_centres(geometry_seed, 64)
     return np.ascontiguousarray(np.concatenate(
         [sphere_points(seed, h), cluster_points(seed, n - h, c, 0.01)], axis=0))
+
+
+def moved_points(points: np.ndarray, seed: int, sigma: float) -> np.ndarray:
+    """The points one time step later: each coordinate moved by
+    sigma * N(0, 1) (draw 3i + j for coordinate j of point i), in FP64, then
+    clamped into the cube and rounded to FP32."""
+    g = normal(stream_seed(seed, TAG_MOVE), points.size).reshape(points.shape)
+    return _to_cube_f32(points.astype(np.float64) + sigma * g)
 
 
 def full_grid_points(level: int) -> np.ndarray:

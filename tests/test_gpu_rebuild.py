@@ -1,0 +1,189 @@
+"""GPU parity of the incremental rebuild (fmmds_rebuild through the C ABI):
+after the points move, rebuilding from the previous tree's order must give
+exactly the tree the oracle builds from the new positions (every table and
+list, bit for bit), whichever order the new positions are given in, however
+many points changed box, and on the fallback that fully sorts."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import parity
+from paper_1301_1704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_1704_amd as F
+    if not os.path.exists(F.LIB_PATH):
+        from paper_1301_1704_amd import _compile
+        _compile.build()
+    F._lib()
+    return F
+
+
+def _in_prev_order(x, perm):
+    """Row k = original point perm[k]."""
+    return np.ascontiguousarray(x[perm])
+
+
+def _rebuild(F, prev, src, recv, prev_order, **kw):
+    if prev_order:
+        src = _in_prev_order(src, prev.host_perm(0))
+        if recv is not None:
+            recv = _in_prev_order(recv, prev.host_perm(1))
+    return F.rebuild(prev, parity.to_gpu(src), None if recv is None else parity.to_gpu(recv),
+                     in_prev_order=prev_order, **kw)
+
+
+CASES = [
+    # name, make(src, recv), L, key_bits, cluster_s, sigma
+    ("shared-uniform-small-move", lambda: (I.uniform_points(201, 40000), None), 6, 64, 0, 1e-3),
+    ("separate-clustered-u32", lambda: (I.sphere_cluster_points(202, 203, 30000),
+                                        I.uniform_points(204, 25000)), 7, 32, 0, 3e-4),
+    ("shared-clustered-s32", lambda: (I.sphere_cluster_points(205, 206, 50000), None), 9, 64, 32,
+     2e-4),
+    ("large-move", lambda: (I.uniform_points(207, 20000), I.uniform_points(208, 7000)), 5, 64, 0,
+     0.2),
+    ("no-move", lambda: (I.uniform_points(209, 30000), None), 7, 64, 0, 0.0),
+]
+
+
+@pytest.mark.parametrize("prev_order", [False, True])
+@pytest.mark.parametrize("name,make,L,kb,s,sigma", CASES, ids=[c[0] for c in CASES])
+def test_rebuild_matches_oracle(F, oracle_lib, name, make, L, kb, s, sigma, prev_order):
+    import torch
+    src, recv = make()
+    _say(f"case {name} L={L} kb={kb} s={s} sigma={sigma} prev_order={prev_order}")
+    prev = F.build(parity.to_gpu(src), None if recv is None else parity.to_gpu(recv),
+                   max_level=L, key_bits=kb, cluster_s=s)
+    torch.cuda.synchronize()
+    src2 = I.moved_points(src, 210, sigma) if sigma > 0 else src
+    recv2 = None if recv is None else (I.moved_points(recv, 211, sigma) if sigma > 0 else recv)
+    g = _rebuild(F, prev, src2, recv2, prev_order, key_bits=kb, cluster_s=s)
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleTree(src2, recv2, key_bits=kb, cluster_s=s, max_level=L)
+    parity.compare_tables(g, o, kb)
+    parity.compare_lists(g, o)
+    # a chain: rebuild from the rebuilt tree after one more step
+    src3 = I.moved_points(src2, 212, sigma) if sigma > 0 else src2
+    recv3 = None if recv2 is None else (I.moved_points(recv2, 213, sigma) if sigma > 0 else recv2)
+    prev.free()
+    g2 = _rebuild(F, g, src3, recv3, prev_order, key_bits=kb, cluster_s=s)
+    torch.cuda.synchronize()
+    o2 = oracle_lib.OracleTree(src3, recv3, key_bits=kb, cluster_s=s, max_level=L)
+    parity.compare_tables(g2, o2, kb)
+    parity.compare_lists(g2, o2)
+    for t in (g, g2):
+        t.free()
+    o.close()
+    o2.close()
+
+
+@pytest.mark.parametrize("prev_order", [False, True])
+def test_fallback_full_sort_for_wide_keys(F, oracle_lib, prev_order):
+    """Level 21 keys (63 bits) plus the index bits do not fit the 64-bit merge
+    value: the rebuild sorts fully and the result is still exact."""
+    import torch
+    src = I.sphere_cluster_points(215, 216, 5000)
+    _say(f"case fallback L=21 prev_order={prev_order}")
+    prev = F.build(parity.to_gpu(src), None, max_level=21, key_bits=64)
+    torch.cuda.synchronize()
+    src2 = I.moved_points(src, 217, 1e-5)
+    g = _rebuild(F, prev, src2, None, prev_order)
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleTree(src2, None, key_bits=64, max_level=21)
+    parity.compare_tables(g, o, 64)
+    parity.compare_lists(g, o)
+    prev.free()
+    g.free()
+    o.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 2049])
+def test_tiny_sets(F, oracle_lib, n):
+    import torch
+    src = I.uniform_points(220 + n, n)
+    prev = F.build(parity.to_gpu(src), None, max_level=4)
+    torch.cuda.synchronize()
+    src2 = I.moved_points(src, 230 + n, 0.05)
+    g = F.rebuild(prev, parity.to_gpu(src2), None)
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleTree(src2, None, key_bits=64, max_level=4)
+    parity.compare_tables(g, o, 64)
+    parity.compare_lists(g, o)
+    prev.free()
+    g.free()
+    o.close()
+
+
+def test_errors(F):
+    import torch
+    a = F.build(parity.to_gpu(I.uniform_points(240, 3000)), None, max_level=5)
+    b = F.build(parity.to_gpu(I.uniform_points(241, 3000)), parity.to_gpu(I.uniform_points(242, 500)),
+                max_level=5)
+    torch.cuda.synchronize()
+    x = parity.to_gpu(I.uniform_points(243, 3000))
+    with pytest.raises(ValueError):
+        F.rebuild(a, parity.to_gpu(I.uniform_points(244, 2999)), None)
+    with pytest.raises(ValueError):
+        F.rebuild(b, x, None)  # b has separate receivers
+    # another max level is refused by the C ABI
+    L = F._lib()
+    import ctypes as C
+    opt, _ = F._build_options(x, None, 6, 64, 0, None, "pool")
+    out = C.POINTER(F.TreeStruct)()
+    assert L.fmmds_rebuild(a._h, x.data_ptr(), None, 0, C.byref(opt), C.byref(out)) == F.ERR_ARG
+    assert L.fmmds_rebuild(a._h, x.data_ptr(), None, 2, C.byref(opt), C.byref(out)) == F.ERR_ARG
+    # a moved point outside the cube is a range error
+    p = I.uniform_points(243, 3000)
+    p[100, 2] = 1.5
+    with pytest.raises(F.FmmdsError) as e:
+        F.rebuild(a, parity.to_gpu(p), None)
+    assert e.value.status == F.ERR_RANGE
+    a.free()
+    b.free()
+
+
+@pytest.mark.timeout(900)
+def test_full_uniform_2x2p24_L8_equals_fresh_build(F):
+    """The benchmark build after one time step (sigma 1e-4): the rebuild from
+    the previous tree equals a fresh build of the moved points, array for
+    array, in both input orders (the fresh build's own parity at this size is
+    covered by the plain full-size test)."""
+    import torch
+    c = I.config_plain_uniform()
+    _say("case rebuild full uniform 2x2^24 L8")
+    prev = F.build(parity.to_gpu(c["src"]), parity.to_gpu(c["recv"]), max_level=8)
+    torch.cuda.synchronize()
+    src2 = I.moved_points(c["src"], 250, 1e-4)
+    recv2 = I.moved_points(c["recv"], 251, 1e-4)
+    fresh = F.build(parity.to_gpu(src2), parity.to_gpu(recv2), max_level=8)
+    for prev_order in (False, True):
+        g = _rebuild(F, prev, src2, recv2, prev_order)
+        torch.cuda.synchronize()
+        assert g.depth == fresh.depth
+        for s in (0, 1):
+            assert np.array_equal(g.host_perm(s), fresh.host_perm(s))
+            assert g.host_sorted_xyz(s).tobytes() == fresh.host_sorted_xyz(s).tobytes()
+            for l in range(9):
+                assert np.array_equal(g.host_keys(s, l), fresh.host_keys(s, l))
+                assert np.array_equal(g.host_begin(s, l), fresh.host_begin(s, l))
+        for l in range(2, 9):
+            for k in (2, 4):
+                for x, y in zip(g.host_list(k, l), fresh.host_list(k, l)):
+                    assert np.array_equal(x, y), (prev_order, k, l)
+        g.free()
+    prev.free()
+    fresh.free()
