@@ -86,3 +86,24 @@ def test_queries_on_null_tree(lib):
     assert lib.fmmds_interactions(None, 2, C.byref(off), C.byref(ent), C.byref(nb),
                                   C.byref(ne)) == F.ERR_ARG
     lib.fmmds_free(None)
+
+
+def test_rebuild_arguments_rejected_on_host(lib):
+    """fmmds_rebuild checks its arguments against the previous tree before
+    any device work (the tree here is a host struct with fake pointers)."""
+    import paper_1301_1704_amd as F
+    t = F.TreeStruct()
+    t.depth, t.key_bits, t.max_level, t.shared, t.n_src, t.n_recv = 5, 64, 5, 1, 10, 10
+    fake = C.c_void_p(0x1000)
+    t.src_perm = t.recv_perm = t.src_sorted_xyz = t.recv_sorted_xyz = 0x1000
+    out = C.POINTER(F.TreeStruct)()
+    ok = _opt(F, max_level=5)
+    assert lib.fmmds_rebuild(None, fake, None, 0, C.byref(ok), C.byref(out)) == F.ERR_ARG
+    assert lib.fmmds_rebuild(C.byref(t), fake, None, 0, None, C.byref(out)) == F.ERR_ARG
+    assert lib.fmmds_rebuild(C.byref(t), fake, None, 2, C.byref(ok), C.byref(out)) == F.ERR_ARG
+    assert lib.fmmds_rebuild(C.byref(t), fake, fake, 0, C.byref(ok), C.byref(out)) == F.ERR_ARG
+    assert lib.fmmds_rebuild(C.byref(t), fake, None, 0, C.byref(_opt(F, max_level=6)),
+                             C.byref(out)) == F.ERR_ARG
+    t.src_perm = None
+    assert lib.fmmds_rebuild(C.byref(t), fake, None, 0, C.byref(ok), C.byref(out)) == F.ERR_ARG
+    assert not out
