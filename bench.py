@@ -79,7 +79,7 @@ KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_coun
                  "zero": "sort.hip", "leaf": "tables.hip", "level": "tables.hip",
                  "max_occupancy": "tables.hip"}
 COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-rebuild "
-                "--no-profile --copy-calibration")
+                "--no-dense --no-profile --copy-calibration")
 
 
 def _kernel_class(name: str):
@@ -154,7 +154,7 @@ def kernel_stats_summary(stats_csv: str, out: str, workload_name: str):
     rows = list(csv.DictReader(open(stats_csv)))
     cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
            "-d <dir> -o run -- python3 <repo>/bench.py --workload " + workload_name +
-           " --no-cpu-baseline --no-batch --no-serving --no-rebuild")
+           " --no-cpu-baseline --no-batch --no-serving --no-rebuild --no-dense")
     lines = [f"# Kernel times (rocprofv3 --kernel-trace --stats), workload `{workload_name}`", "",
              "```", cmd, f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
              f"{os.path.relpath(out, ROOT)} --workload {workload_name}", "```", "",
@@ -374,6 +374,35 @@ def bench_rebuild(F, torch, c, kw, reps=5, sigma=1e-4):
     return res
 
 
+def bench_dense(F, torch, src, recv, kw, reps=5):
+    """The same build through the dense-histogram construction (Algorithms
+    1, 3, 4 with 8^L counters per level and direct ScannedRank lookups)."""
+    def timed(fn):
+        fn().free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn().free()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+    sort_ms = timed(lambda: F.build(src, recv, **kw))
+    dense_ms = timed(lambda: F.build_dense(src, recv, **kw))
+    F.profile_reset()
+    F.profile_enable(True)
+    F.build_dense(src, recv, **kw).free()
+    torch.cuda.synchronize()
+    F.profile_enable(False)
+    br = F.profile_read()
+    n_pts = src.shape[0] + (0 if recv is None else recv.shape[0])
+    res = {"workload": "the benchmark build", "sort_path_ms": sort_ms, "dense_ms": dense_ms,
+           "points_per_s": n_pts / (dense_ms * 1e-3), "dense_vs_sort": sort_ms / dense_ms,
+           "kernels": {k: {"launches": v["launches"],
+                           "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2)}
+                       for k, v in br.items()}}
+    log(f"dense variant: {dense_ms:.3f} ms vs sort path {sort_ms:.3f} ms")
+    return res
+
+
 def bench_serving(F, torch, args):
     """Continuous-batching serving of rebuild requests from 64 moving particle
     systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
@@ -434,6 +463,8 @@ def main():
                     help="skip the partition / source box type measurement")
     ap.add_argument("--no-rebuild", action="store_true",
                     help="skip the incremental rebuild measurement")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense-histogram variant measurement")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -557,6 +588,8 @@ def main():
         line["box_types"] = bench_box_types(F, torch, src, recv, kw)
     if not args.no_rebuild:
         line["rebuild"] = bench_rebuild(F, torch, c, kw)
+    if not args.no_dense and c["max_level"] <= 8:
+        line["dense"] = bench_dense(F, torch, src, recv, kw)
     if not args.no_batch:
         line["batched"] = bench_batched(F, torch, args)
     if not args.no_serving:

@@ -124,6 +124,20 @@ fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv
                          uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
 
 /*
+ * The same build through the paper's dense-histogram construction (Algorithm
+ * 1's per-box occupancy counters with atomic ranks, Algorithm 3's scans of
+ * all 8^l boxes per level, and E2 / E4 entries looked up directly in the
+ * dense ScannedRank by neighbor coordinates, Algorithm 4), made
+ * deterministic: the result is exactly the tree fmmds_build returns for the
+ * same arguments. Arguments, ownership and errors as fmmds_build, plus
+ * FMMDS_ERR_ARG when opt->max_level exceeds 8 (three dense arrays of 8^l
+ * 32-bit counters per level and point set live during the call). A finest
+ * box holding more than 4096 points is put in order by a sort instead.
+ */
+fmmds_status fmmds_build_dense(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
+                               uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
+
+/*
  * Rebuild after the points moved (the dynamic problems of Section 1, where
  * the structures are rebuilt every time step), reusing the order of a
  * previous tree: only points whose finest-level box changed are sorted, and

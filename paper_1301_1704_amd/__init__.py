@@ -74,6 +74,9 @@ def _lib():
         L.fmmds_build.argtypes = [_vp, _u32, _vp, _u32, C.POINTER(Options),
                                   C.POINTER(C.POINTER(TreeStruct))]
         L.fmmds_build.restype = C.c_int
+        L.fmmds_build_dense.argtypes = [_vp, _u32, _vp, _u32, C.POINTER(Options),
+                                        C.POINTER(C.POINTER(TreeStruct))]
+        L.fmmds_build_dense.restype = C.c_int
         L.fmmds_rebuild.argtypes = [C.POINTER(TreeStruct), _vp, _vp, _u32, C.POINTER(Options),
                                     C.POINTER(C.POINTER(TreeStruct))]
         L.fmmds_rebuild.restype = C.c_int
@@ -133,7 +136,7 @@ def exported_symbols():
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
             "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types",
-            "fmmds_near_field", "fmmds_rebuild"]
+            "fmmds_near_field", "fmmds_rebuild", "fmmds_build_dense"]
 
 
 class DisplaceSet(C.Structure):
@@ -432,6 +435,21 @@ def build(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int 
                        0 if recv is None else recv.shape[0], C.byref(opt), C.byref(out))
     if st != OK:
         raise FmmdsError(st, "fmmds_build")
+    return Tree(out, keep)
+
+
+def build_dense(src, recv=None, *, max_level: int, key_bits: int = 64, cluster_s: int = 0,
+                stream=None, allocator: str = "pool") -> Tree:
+    """The same build through the dense-histogram construction
+    (fmmds_build_dense, max_level <= 8); returns the tree build() returns."""
+    L = _lib()
+    opt, keep = _build_options(src, recv, max_level, key_bits, cluster_s, stream, allocator)
+    out = C.POINTER(TreeStruct)()
+    st = L.fmmds_build_dense(src.data_ptr(), src.shape[0],
+                             None if recv is None else recv.data_ptr(),
+                             0 if recv is None else recv.shape[0], C.byref(opt), C.byref(out))
+    if st != OK:
+        raise FmmdsError(st, "fmmds_build_dense")
     return Tree(out, keep)
 
 

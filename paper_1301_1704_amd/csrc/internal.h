@@ -27,6 +27,7 @@ struct DevMeta {
   uint32_t max_occ[2][kMaxLevel + 1];
   uint64_t list_total[2][kMaxLevel + 1];  // [0] = E2, [1] = E4
   uint32_t inc_counts[2][2];              // incremental rebuild: stayers, movers per set
+  uint32_t dense_big[2];                  // dense variant: finest boxes ordered by blocks
 };
 
 // Sort elements: with `packed`, one uint64 holding (key << 32 | index) for keys
@@ -115,6 +116,33 @@ void launch_inc_merge(bool packed, const uint64_t* st_v, const uint32_t* st_slot
                       const uint64_t* mv_v, const uint32_t* mv_slot, uint32_t nm,
                       const float* xyz, uint32_t ib, uint64_t* sk, uint32_t* sv,
                       float* sorted_xyz, hipStream_t s);  // xyz indexed by slot
+
+// ---- dense.hip (the dense-histogram variant, max level <= 8)
+constexpr uint32_t kDenseMaxLevel = 8;
+constexpr uint32_t kDenseCanonMax = 4096;  // largest finest box put in order on the device
+void launch_dense_count(const float* xyz, uint32_t n, uint32_t L, uint32_t* bin, uint32_t* key,
+                        uint32_t* rank, uint32_t* err, hipStream_t s);
+void launch_dense_reduce(const uint32_t* fine, uint32_t n_coarse, uint32_t* coarse,
+                         hipStream_t s);
+uint32_t dense_scan_tiles(uint32_t nbox);
+void launch_dense_scan(bool key64, const uint32_t* bin, uint32_t nbox, uint32_t* sbin,
+                       uint32_t* srank, void* keys, uint32_t* begin, uint32_t* n_out,
+                       uint32_t* max_occ, uint64_t* status, uint32_t* tile_counter,
+                       hipStream_t s);
+void launch_dense_links(bool key64, const void* keys, const uint32_t* n_p, uint32_t cap,
+                        const uint32_t* bin_fine, const uint32_t* srank_fine,
+                        const uint32_t* n_fine_p, uint32_t* child, uint8_t* mask,
+                        const void* keys_fine, uint32_t cap_fine, uint32_t* parent_fine,
+                        const uint32_t* srank, hipStream_t s);
+void launch_dense_order(const uint32_t* key, const uint32_t* rank, uint32_t n,
+                        const uint32_t* sbin, const uint32_t* begin, const uint32_t* n_boxes,
+                        uint32_t cap_boxes, uint32_t* tmp, uint32_t* perm, uint32_t* big,
+                        uint32_t* n_big, const float* xyz, float* sorted_xyz, hipStream_t s);
+void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_recv, const void* rkeys,
+                        const uint32_t* bin_up, const uint32_t* bin_cur,
+                        const uint32_t* srank_cur, uint32_t* cnt2, uint32_t* cnt4,
+                        const uint32_t* off2, const uint32_t* off4, uint32_t* ent2,
+                        uint32_t* ent4, hipStream_t s);
 
 // ---- batch.hip kernels
 struct LevelPtrs {

@@ -323,13 +323,13 @@ void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 enum KernelClass {
   K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
-  K_REBASE, K_CLASSIFY, K_PLACE, K_NCLASS
+  K_REBASE, K_CLASSIFY, K_PLACE, K_DENSE, K_NCLASS
 };
 const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
                                           "sort_pass", "leaf",        "level",
                                           "max_occupancy", "list_count", "scan_counts",
                                           "list_fill",     "batch_rebase", "inc_classify",
-                                          "inc_place"};
+                                          "inc_place",     "dense"};
 
 struct ClassStat {
   uint64_t launches = 0;
@@ -414,7 +414,8 @@ uint32_t index_bits(uint32_t n) { return n <= 2 ? 1u : 32u - (uint32_t)__builtin
 // (prev_order: the coordinates are given in prev's sorted order).
 fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, uint32_t n_recv,
                    const fmmds_options* opt, fmmds_tree** out,
-                   const fmmds_tree* prev = nullptr, bool prev_order = false) {
+                   const fmmds_tree* prev = nullptr, bool prev_order = false,
+                   bool dense = false) {
   const bool shared = recv_xyz == nullptr;
   if (shared) n_recv = n_src;
   if (!src_xyz || !opt || n_src == 0 || n_recv == 0 || n_src >= 0xFFFFFFFFu ||
@@ -425,6 +426,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
   if (opt->reserved != 0 || ((opt->alloc == nullptr) != (opt->release == nullptr)))
     return FMMDS_ERR_ARG;
 
+  if (dense && opt->max_level > kDenseMaxLevel) return FMMDS_ERR_ARG;
   const uint32_t L = opt->max_level;
   const bool key64 = opt->key_bits == 64;
   const bool packed = 3 * L <= 32;
@@ -484,6 +486,10 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       words += (size_t)np * sort_tiles(n, kSortItemsDefault) * 256 + 2 * div_up(n, kCompTile);
       for (uint32_t l = 0; l < L; ++l) words += div_up(level_cap(n, l + 1), kCompTile);
       tickets += np + 2 + L;
+      if (dense) {
+        for (uint32_t l = 0; l <= L; ++l) words += dense_scan_tiles(1u << (3 * l));
+        tickets += L + 1;
+      }
     }
     const size_t meta_b = round_up(sizeof(DevMeta), 256);
     const size_t hist_b = round_up(2 * kMaxPasses * 256 * 4, 256);
@@ -558,6 +564,17 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       }
     }
 
+    // Dense variant: per set and level the occupancy counters (Bin), their
+    // scan (ScannedBin) and the exclusive nonempty rank (ScannedRank), plus
+    // every point's finest box and provisional rank.
+    struct DenseSet {
+      uint32_t* bin[kMaxLevel + 1] = {};
+      uint32_t* sbin[kMaxLevel + 1] = {};
+      uint32_t* srank[kMaxLevel + 1] = {};
+      uint32_t* key = nullptr;
+      uint32_t* rank = nullptr;
+    } dn[2];
+
     for (int s = 0; s < nsets; ++s) {
       SetBufs& S = sets[s];
       const uint32_t n = S.n;
@@ -590,6 +607,47 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           B.mask = (uint8_t*)tp;
           tp += round_up(c, 256);
         }
+      }
+
+      if (dense) {
+        // Algorithm 1 at level L, the counters of the coarser levels, then
+        // Algorithm 3 per level and the parent / child links.
+        DenseSet& Dn = dn[s];
+        for (uint32_t l = 0; l <= L; ++l) {
+          const size_t nb = (size_t)1 << (3 * l);
+          Dn.bin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+          Dn.sbin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+          Dn.srank[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+        }
+        Dn.key = temps.get<uint32_t>(n);
+        Dn.rank = temps.get<uint32_t>(n);
+        const size_t nbL = (size_t)1 << (3 * L);
+        P.run(K_ZERO, (double)nbL * 4, [&] { launch_zero(Dn.bin[L], nbL * 4, st); });
+        P.run(K_DENSE, (double)n * (12 + 8), [&] {
+          launch_dense_count(S.xyz, n, L, Dn.bin[L], Dn.key, Dn.rank, &meta->err_range, st);
+        });
+        for (int l = (int)L - 1; l >= 0; --l)
+          P.run(K_DENSE, (double)(1u << (3 * l)) * 36, [&] {
+            launch_dense_reduce(Dn.bin[l + 1], 1u << (3 * l), Dn.bin[l], st);
+          });
+        for (uint32_t l = 0; l <= L; ++l) {
+          const uint32_t nb = 1u << (3 * l);
+          uint64_t* stw = sa.take_words(dense_scan_tiles(nb));
+          uint32_t* tk = sa.take_ticket();
+          P.run(K_DENSE, (double)nb * 12, [&] {
+            launch_dense_scan(key64, Dn.bin[l], nb, Dn.sbin[l], Dn.srank[l], S.lv[l].key,
+                              S.lv[l].begin, &meta->n_boxes[s][l], &meta->max_occ[s][l], stw, tk,
+                              st);
+          });
+        }
+        for (uint32_t l = 0; l < L; ++l)
+          P.run(K_DENSE, 0.0, [&] {
+            launch_dense_links(key64, S.lv[l].key, &meta->n_boxes[s][l], S.lv[l].cap,
+                               Dn.bin[l + 1], Dn.srank[l + 1], &meta->n_boxes[s][l + 1],
+                               S.lv[l].child, S.lv[l].mask, S.lv[l + 1].key, S.lv[l + 1].cap,
+                               S.lv[l + 1].parent, Dn.srank[l], st);
+          });
+        continue;  // the point order follows once the largest box is known
       }
 
       // ---- keys and sort
@@ -699,6 +757,46 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     for (int s = 0; s < 2; ++s)
       for (uint32_t l = 0; l <= L; ++l) nb[s][l] = hm->n_boxes[s < nsets ? s : 0][l];
 
+    // Dense variant: the point order. Boxes of up to kDenseCanonMax points
+    // are put in index order on the device; beyond that the set's points are
+    // sorted (its tables stay those of the dense scans: the same values).
+    for (int s = 0; dense && s < nsets; ++s) {
+      SetBufs& S = sets[s];
+      const uint32_t n = S.n;
+      if (hm->max_occ[s][L] <= kDenseCanonMax) {
+        uint32_t* tmp = temps.get<uint32_t>(n);
+        uint32_t* big = temps.get<uint32_t>(std::max<uint32_t>(nb[s][L], 1));
+        P.run(K_DENSE, (double)n * (8 + 4 + 4 + 4 + 4 + 4 + 12 + 12), [&] {
+          launch_dense_order(dn[s].key, dn[s].rank, n, dn[s].sbin[L], S.lv[L].begin,
+                             &meta->n_boxes[s][L], nb[s][L], tmp, S.perm, big,
+                             &meta->dense_big[s], S.xyz, S.sorted_xyz, st);
+        });
+        continue;
+      }
+      uint32_t* h = hist + s * kMaxPasses * 256;
+      uint32_t* g = goff + s * kMaxPasses * 256;
+      P.run(K_KEYGEN, 0.0, [&] {
+        launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
+      });
+      P.run(K_DIGITS, 0.0, [&] { launch_digit_offsets(h, g, n_pass, st); });
+      for (uint32_t p = 0; p < n_pass; ++p) {
+        const int a = p & 1, b = a ^ 1;
+        uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
+        uint32_t* tk = sa.take_ticket();
+        P.run(K_SORT, 0.0, [&] {
+          launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, (packed ? 32 : 0) + 8 * p,
+                           g + p * 256, stw, tk, st, kSortItemsDefault);
+        });
+      }
+      uint64_t* stw = sa.take_words(div_up(n, kCompTile));
+      uint32_t* tk = sa.take_ticket();
+      const int fin = n_pass & 1;
+      P.run(K_LEAF, 0.0, [&] {
+        launch_leaf(packed, key64, sb.k[fin], sb.v[fin], S.xyz, n, S.perm, S.sorted_xyz,
+                    S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L], st);
+      });
+    }
+
     // ---- lists, levels 2..D
     size_t lwords = 0, lmax = 0;
     for (uint32_t l = 2; l <= D; ++l) {
@@ -741,7 +839,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
       // level 2 only: the fill of each level writes the next level's counts
-      if (l == 2)
+      if (dense)
+        P.run(K_DENSE, 0.0, [&] {
+          launch_dense_lists(key64, false, l, nr, sets[rs].lv[l].key, dn[0].bin[l - 1],
+                             dn[0].bin[l], dn[0].srank[l], cnt, cnt + round_up(nr, 4), nullptr,
+                             nullptr, nullptr, nullptr, st);
+        });
+      else if (l == 2)
         P.run(K_COUNT, side + (double)nr * 8,
               [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
       LB.off[0] = impl->outs.get<uint32_t>((size_t)nr + 1);
@@ -760,6 +864,15 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       for (int k = 0; k < 2; ++k) {
         LB.total[k] = hm->list_total[k][l];
         LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
+      }
+      if (dense) {
+        P.run(K_DENSE, 0.0, [&] {
+          launch_dense_lists(key64, true, l, nr, sets[rs].lv[l].key, dn[0].bin[l - 1],
+                             dn[0].bin[l], dn[0].srank[l], nullptr, nullptr, LB.off[0],
+                             LB.off[1], LB.ent[0], LB.ent[1], st);
+        });
+        impl->n_recv_boxes[l] = nr;
+        continue;
       }
       double next_b = 0.0;  // level + 1 counts: masks and first children in, two counts out
       if (l < D) {
@@ -1516,6 +1629,13 @@ fmmds_status fmmds_rebuild(const fmmds_tree* prev, const float* src_xyz, const f
     return FMMDS_ERR_ARG;
   return fmmds::build(src_xyz, prev->n_src, recv_xyz, prev->n_recv, opt, out, prev,
                       in_prev_order != 0);
+}
+
+fmmds_status fmmds_build_dense(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
+                               uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out) {
+  if (!out) return FMMDS_ERR_ARG;
+  *out = nullptr;
+  return fmmds::build(src_xyz, n_src, recv_xyz, n_recv, opt, out, nullptr, false, true);
 }
 
 fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,
