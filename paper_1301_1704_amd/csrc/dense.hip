@@ -20,7 +20,7 @@
 // points instead (the box tables are the same either way).
 //
 // Lists come out in ascending rank: the receiver's parent's 27 neighbors are
-// sorted by Morton index, and walking them in that order, each followed by
+// ordered by Morton index, and taking them in that order, each followed by
 // its eight children in octant order, visits the candidate boxes in
 // ascending Morton index, hence ascending rank.
 #include "device.h"
@@ -248,68 +248,195 @@ __global__ __launch_bounds__(256) void k_dense_gather(const uint32_t* __restrict
     out[e] = xyz[perm[e]];
 }
 
-// Lists of the receiver boxes of level l (2 <= l <= 8), a thread per box:
-// count (FILL false) or write (FILL true) the E2 and E4 entries.
-template <typename KeyT, bool FILL>
-__global__ __launch_bounds__(256) void k_dense_lists(
-    uint32_t l, uint32_t n_recv, const KeyT* __restrict__ rkeys,
-    const uint32_t* __restrict__ bin_up, const uint32_t* __restrict__ bin_cur,
-    const uint32_t* __restrict__ srank_cur, uint32_t* __restrict__ cnt2,
-    uint32_t* __restrict__ cnt4, const uint32_t* __restrict__ off2,
-    const uint32_t* __restrict__ off4, uint32_t* __restrict__ ent2, uint32_t* __restrict__ ent4) {
-  const uint64_t b = blockIdx.x * 256ull + threadIdx.x;
-  if (b >= n_recv) return;
-  const uint32_t key = (uint32_t)rkeys[b];
-  const int x = (int)compact3(key), y = (int)compact3(key >> 1), z = (int)compact3(key >> 2);
-  const int side_up = 1 << (l - 1);
-  // The parent's neighbors at level l - 1, sorted by Morton index (absent
-  // ones as 0xFFFFFFFF, sorted last).
-  uint32_t nk[27];
+// Lists of the receiver boxes of level l (2 <= l <= 8). One half-wave per
+// receiver parent p at level l - 1: lane t < 27 takes p's neighbor at offset
+// (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1), keeps it if the dense source counter
+// of level l - 1 says it is nonempty, and reads its eight child counters at
+// level l (the first child's rank is the dense ScannedRank there). Ordering
+// the kept neighbors by Morton index and their children by octant gives the
+// union U of the candidates in ascending rank. Counting: for each receiver
+// child of p, its E2 count is the number of U entries within one box, and
+// E4 the rest. Filling: U goes to LDS with, per entry, the mask of receiver
+// octants it is adjacent to, and the whole wave splits U per receiver child
+// with one ballot per 64 entries (E2 lanes to the E2 list, the others to
+// the E4 list), two parents per wave.
+struct DenseListArgs {
+  uint32_t l, n_up;          // level; receiver boxes of level l - 1 (the parents)
+  const void* rkey_up;       // their keys
+  const uint8_t* rmask_up;   // their receiver child masks
+  const uint32_t* rchild_up; // their first receiver children
+  const uint32_t* bin_up;    // dense source counters, level l - 1
+  const uint32_t* bin_cur;   // dense source counters, level l
+  const uint32_t* srank_cur; // dense exclusive source ranks, level l
+};
+
+// One half-wave: the kept neighbor of lane t (its key, child mask, first
+// child rank, axis offsets) and its position and offset in U.
+struct Neighbor {
+  uint32_t m, cb, upos, total;
+  int dx, dy, dz;
+};
+
+template <typename KeyT>
+__device__ __forceinline__ Neighbor dense_neighbor(const DenseListArgs& a, uint64_t p, bool live,
+                                                   uint32_t j) {
+  Neighbor nb{};
+  uint32_t key = 0xFFFFFFFFu;
+  bool keep = false;
+  if (live && j < 27) {
+    const uint32_t pk = (uint32_t)((const KeyT*)a.rkey_up)[p];
+    const int side = 1 << (a.l - 1);
+    nb.dx = (int)(j % 3) - 1, nb.dy = (int)(j / 3 % 3) - 1, nb.dz = (int)(j / 9) - 1;
+    const int x = (int)compact3(pk) + nb.dx, y = (int)compact3(pk >> 1) + nb.dy,
+              z = (int)compact3(pk >> 2) + nb.dz;
+    if (x >= 0 && y >= 0 && z >= 0 && x < side && y < side && z < side) {
+      key = spread3_10((uint32_t)x) | spread3_10((uint32_t)y) << 1 | spread3_10((uint32_t)z) << 2;
+      keep = a.bin_up[key] > 0;
+    }
+  }
+  if (keep) {
+    const uint64_t c8 = (uint64_t)key << 3;
+    const uint4 lo = ((const uint4*)(a.bin_cur + c8))[0], hi = ((const uint4*)(a.bin_cur + c8))[1];
+    nb.m = (lo.x > 0) | (lo.y > 0) << 1 | (lo.z > 0) << 2 | (lo.w > 0) << 3 | (hi.x > 0) << 4 |
+           (hi.y > 0) << 5 | (hi.z > 0) << 6 | (hi.w > 0) << 7;
+    nb.cb = a.srank_cur[c8];
+  }
+  if (!keep) key = 0xFFFFFFFFu;
+  // position in Morton order among the kept neighbors, and offset in U
+  const uint32_t c = (uint32_t)__popc(nb.m);
+  uint32_t upos = 0, total = 0;
+#pragma unroll 1
+  for (uint32_t i = 0; i < 27; ++i) {
+    const uint32_t ki = (uint32_t)__shfl(key, (int)i, 32), ci = (uint32_t)__shfl(c, (int)i, 32);
+    upos += ki < key ? ci : 0u;
+    total += ci;
+  }
+  nb.upos = upos;
+  nb.total = total;
+  return nb;
+}
+
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_dense_pcount(DenseListArgs a, uint32_t* __restrict__ cnt2,
+                                                      uint32_t* __restrict__ cnt4) {
+  const uint32_t j = threadIdx.x & 31u, h = threadIdx.x >> 5;
+  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  if (p >= a.n_up) return;  // whole half-wave
+  const Neighbor nb = dense_neighbor<KeyT>(a, p, true, j);
+  // Children of the neighbor adjacent to a receiver child whose axis bit is
+  // 0 / 1 (offset 0: all; +1: child bit 0 next to receiver bit 1; -1: the
+  // mirror); per receiver octant q the number of them, packed 6 bits each.
+  const uint32_t ax0 = nb.dx == 0 ? 0xFFu : (nb.dx < 0 ? 0xAAu : 0u);
+  const uint32_t ax1 = nb.dx == 0 ? 0xFFu : (nb.dx > 0 ? 0x55u : 0u);
+  const uint32_t ay0 = nb.dy == 0 ? 0xFFu : (nb.dy < 0 ? 0xCCu : 0u);
+  const uint32_t ay1 = nb.dy == 0 ? 0xFFu : (nb.dy > 0 ? 0x33u : 0u);
+  const uint32_t az0 = nb.dz == 0 ? 0xFFu : (nb.dz < 0 ? 0xF0u : 0u);
+  const uint32_t az1 = nb.dz == 0 ? 0xFFu : (nb.dz > 0 ? 0x0Fu : 0u);
+  uint32_t wa = 0, wb = 0;
 #pragma unroll
-  for (int t = 0; t < 27; ++t) {
-    const int px = (x >> 1) + t % 3 - 1, py = (y >> 1) + (t / 3) % 3 - 1, pz = (z >> 1) + t / 9 - 1;
-    const bool in = px >= 0 && py >= 0 && pz >= 0 && px < side_up && py < side_up && pz < side_up;
-    nk[t] = in ? (spread3_10((uint32_t)px) | spread3_10((uint32_t)py) << 1 |
-                  spread3_10((uint32_t)pz) << 2)
-               : 0xFFFFFFFFu;
+  for (uint32_t q = 0; q < 8; ++q) {
+    const uint32_t adj = ((q & 1u) ? ax1 : ax0) & ((q & 2u) ? ay1 : ay0) & ((q & 4u) ? az1 : az0);
+    const uint32_t c2 = (uint32_t)__popc(nb.m & adj);
+    if (q < 4) wa |= c2 << (6 * q);
+    else wb |= c2 << (6 * (q - 4));
   }
 #pragma unroll
-  for (int i = 0; i < 26; ++i)
+  for (int o = 16; o > 0; o >>= 1) {
+    wa += (uint32_t)__shfl_xor(wa, o, 32);
+    wb += (uint32_t)__shfl_xor(wb, o, 32);
+  }
+  const uint32_t rmask = a.rmask_up[p], rfirst = a.rchild_up[p];
+  if (j < (uint32_t)__popc(rmask)) {
+    uint32_t mm = rmask;
+    for (uint32_t t = 0; t < j; ++t) mm &= mm - 1;
+    const uint32_t q = (uint32_t)__builtin_ctz(mm);
+    const uint32_t n2 = q < 4 ? (wa >> (6 * q)) & 63u : (wb >> (6 * (q - 4))) & 63u;
+    cnt2[rfirst + j] = n2;
+    cnt4[rfirst + j] = nb.total - n2;
+  }
+}
+
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_dense_pfill(DenseListArgs a,
+                                                     const uint32_t* __restrict__ off2,
+                                                     const uint32_t* __restrict__ off4,
+                                                     uint32_t* __restrict__ ent2,
+                                                     uint32_t* __restrict__ ent4) {
+  __shared__ uint32_t s_rank[8][256];
+  __shared__ uint8_t s_adj[8][256];
+  const uint32_t lane = threadIdx.x & 63u, j = lane & 31u, h = threadIdx.x >> 5;
+  const uint64_t p = (uint64_t)blockIdx.x * 8 + h;
+  if ((uint64_t)blockIdx.x * 8 + (h & ~1u) >= a.n_up) return;  // whole wave
+  const bool live = p < a.n_up;
+  uint32_t rmask = 0, rfirst = 0;
+  if (live) {
+    rmask = a.rmask_up[p];
+    rfirst = a.rchild_up[p];
+  }
+  uint32_t my_o2 = 0, my_o4 = 0;  // lane j: list offsets of receiver child j
+  if (j < (uint32_t)__popc(rmask)) {
+    my_o2 = off2[rfirst + j];
+    my_o4 = off4[rfirst + j];
+  }
+  const Neighbor nb = dense_neighbor<KeyT>(a, p, live, j);
+  {
+    // receiver octants a child with axis bit 0 / 1 is adjacent to (receivers
+    // with the x / y / z bit set: 0xAA / 0xCC / 0xF0)
+    const uint32_t xm0 = nb.dx == 0 ? 0xFFu : (nb.dx > 0 ? 0xAAu : 0u);
+    const uint32_t xm1 = nb.dx == 0 ? 0xFFu : (nb.dx < 0 ? 0x55u : 0u);
+    const uint32_t ym0 = nb.dy == 0 ? 0xFFu : (nb.dy > 0 ? 0xCCu : 0u);
+    const uint32_t ym1 = nb.dy == 0 ? 0xFFu : (nb.dy < 0 ? 0x33u : 0u);
+    const uint32_t zm0 = nb.dz == 0 ? 0xFFu : (nb.dz > 0 ? 0xF0u : 0u);
+    const uint32_t zm1 = nb.dz == 0 ? 0xFFu : (nb.dz < 0 ? 0x0Fu : 0u);
 #pragma unroll
-    for (int t = 0; t < 26 - i; ++t) {
-      const uint32_t a = nk[t], c = nk[t + 1];
-      nk[t] = min(a, c);
-      nk[t + 1] = max(a, c);
-    }
-  uint32_t n2 = 0, n4 = 0;
-  uint32_t p2 = FILL ? off2[b] : 0, p4 = FILL ? off4[b] : 0;
-#pragma unroll
-  for (int t = 0; t < 27; ++t) {
-    const uint32_t s = nk[t];
-    if (s == 0xFFFFFFFFu || bin_up[s] == 0) continue;
-    const int sx = (int)compact3(s), sy = (int)compact3(s >> 1), sz = (int)compact3(s >> 2);
-    const uint64_t c8 = (uint64_t)s << 3;
-    const uint4 lo = ((const uint4*)(bin_cur + c8))[0], hi = ((const uint4*)(bin_cur + c8))[1];
-    const uint32_t occ[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      if (occ[o] == 0) continue;
-      const int dx = 2 * sx + (o & 1) - x, dy = 2 * sy + ((o >> 1) & 1) - y,
-                dz = 2 * sz + ((o >> 2) & 1) - z;
-      const bool near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-      if (FILL) {
-        const uint32_t r = srank_cur[c8 + o];
-        if (near) ent2[p2++] = r;
-        else ent4[p4++] = r;
-      } else {
-        n2 += near ? 1u : 0u;
-        n4 += near ? 0u : 1u;
+    for (uint32_t o = 0; o < 8; ++o) {
+      if (nb.m & (1u << o)) {
+        const uint32_t r = (uint32_t)__popc(nb.m & ((1u << o) - 1u));
+        s_rank[h][nb.upos + r] = nb.cb + r;
+        s_adj[h][nb.upos + r] = (uint8_t)(((o & 1u) ? xm1 : xm0) & ((o & 2u) ? ym1 : ym0) &
+                                          ((o & 4u) ? zm1 : zm0));
       }
     }
   }
-  if (!FILL) {
-    cnt2[b] = n2;
-    cnt4[b] = n4;
+  __builtin_amdgcn_wave_barrier();
+  uint32_t u[2][4], ad[2], T[2];
+#pragma unroll
+  for (uint32_t hh = 0; hh < 2; ++hh) {
+    T[hh] = (uint32_t)__builtin_amdgcn_readlane(nb.total, 32 * hh);
+    ad[hh] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t idx = 64u * k + lane;
+      u[hh][k] = idx < T[hh] ? s_rank[(h & ~1u) + hh][idx] : 0u;
+      ad[hh] |= (idx < T[hh] ? (uint32_t)s_adj[(h & ~1u) + hh][idx] : 0u) << (8 * k);
+    }
+  }
+#pragma unroll
+  for (uint32_t hh = 0; hh < 2; ++hh) {
+    const uint32_t n_chunks = (T[hh] + 63u) >> 6;
+    uint32_t qm = (uint32_t)__builtin_amdgcn_readlane(rmask, 32 * hh), child = 32 * hh;
+#pragma unroll 1
+    while (qm) {
+      const uint32_t q = __builtin_ctz(qm);
+      qm &= qm - 1;
+      uint32_t* d2 = ent2 + (uint32_t)__builtin_amdgcn_readlane(my_o2, child);
+      uint32_t* d4 = ent4 + (uint32_t)__builtin_amdgcn_readlane(my_o4, child);
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        if (k < n_chunks) {
+          const uint32_t rem = T[hh] - 64u * k;
+          const bool is2 = (ad[hh] >> (8 * k + q)) & 1u;
+          const uint64_t b2 = __ballot(is2);
+          const uint32_t i2 = mbcnt(b2);
+          uint32_t* dst = is2 ? d2 + i2 : d4 + (lane - i2);
+          if (lane < rem) *dst = u[hh][k];
+          const uint32_t n2 = (uint32_t)__popcll(b2);
+          d2 += n2;
+          d4 += min(rem, 64u) - n2;
+        }
+      }
+      ++child;
+    }
   }
 }
 
@@ -375,22 +502,28 @@ void launch_dense_order(const uint32_t* key, const uint32_t* rank, uint32_t n,
                      (P3*)sorted_xyz);
 }
 
-void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_recv, const void* rkeys,
+void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_up, const void* rkey_up,
+                        const uint8_t* rmask_up, const uint32_t* rchild_up,
                         const uint32_t* bin_up, const uint32_t* bin_cur,
                         const uint32_t* srank_cur, uint32_t* cnt2, uint32_t* cnt4,
                         const uint32_t* off2, const uint32_t* off4, uint32_t* ent2,
                         uint32_t* ent4, hipStream_t s) {
-  if (n_recv == 0) return;
-  const uint32_t grid = div_up(n_recv, 256);
-#define FMMDS_DL(K, F)                                                                         \
-  hipLaunchKernelGGL((k_dense_lists<K, F>), dim3(grid), dim3(256), 0, s, l, n_recv,            \
-                     (const K*)rkeys, bin_up, bin_cur, srank_cur, cnt2, cnt4, off2, off4, ent2,   \
-                     ent4)
-  if (key64 && fill) FMMDS_DL(uint64_t, true);
-  else if (key64) FMMDS_DL(uint64_t, false);
-  else if (fill) FMMDS_DL(uint32_t, true);
-  else FMMDS_DL(uint32_t, false);
-#undef FMMDS_DL
+  if (n_up == 0) return;
+  const DenseListArgs a{l, n_up, rkey_up, rmask_up, rchild_up, bin_up, bin_cur, srank_cur};
+  const uint32_t grid = div_up(n_up, 8);
+  if (fill) {
+    if (key64)
+      hipLaunchKernelGGL(k_dense_pfill<uint64_t>, dim3(grid), dim3(256), 0, s, a, off2, off4,
+                         ent2, ent4);
+    else
+      hipLaunchKernelGGL(k_dense_pfill<uint32_t>, dim3(grid), dim3(256), 0, s, a, off2, off4,
+                         ent2, ent4);
+  } else {
+    if (key64)
+      hipLaunchKernelGGL(k_dense_pcount<uint64_t>, dim3(grid), dim3(256), 0, s, a, cnt2, cnt4);
+    else
+      hipLaunchKernelGGL(k_dense_pcount<uint32_t>, dim3(grid), dim3(256), 0, s, a, cnt2, cnt4);
+  }
 }
 
 }  // namespace fmmds

@@ -138,11 +138,12 @@ void launch_dense_order(const uint32_t* key, const uint32_t* rank, uint32_t n,
                         const uint32_t* sbin, const uint32_t* begin, const uint32_t* n_boxes,
                         uint32_t cap_boxes, uint32_t* tmp, uint32_t* perm, uint32_t* big,
                         uint32_t* n_big, const float* xyz, float* sorted_xyz, hipStream_t s);
-void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_recv, const void* rkeys,
+void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_up, const void* rkey_up,
+                        const uint8_t* rmask_up, const uint32_t* rchild_up,
                         const uint32_t* bin_up, const uint32_t* bin_cur,
                         const uint32_t* srank_cur, uint32_t* cnt2, uint32_t* cnt4,
                         const uint32_t* off2, const uint32_t* off4, uint32_t* ent2,
-                        uint32_t* ent4, hipStream_t s);
+                        uint32_t* ent4, hipStream_t s);  // n_up: receiver boxes of level l - 1
 
 // ---- batch.hip kernels
 struct LevelPtrs {

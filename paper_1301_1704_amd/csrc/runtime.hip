@@ -323,13 +323,14 @@ void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 enum KernelClass {
   K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
-  K_REBASE, K_CLASSIFY, K_PLACE, K_DENSE, K_NCLASS
+  K_REBASE, K_CLASSIFY, K_PLACE, K_DCOUNT, K_DSCAN, K_DORDER, K_DLIST, K_NCLASS
 };
 const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
                                           "sort_pass", "leaf",        "level",
                                           "max_occupancy", "list_count", "scan_counts",
                                           "list_fill",     "batch_rebase", "inc_classify",
-                                          "inc_place",     "dense"};
+                                          "inc_place",     "dense_count",  "dense_scan",
+                                          "dense_order",   "dense_lists"};
 
 struct ClassStat {
   uint64_t launches = 0;
@@ -623,25 +624,25 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         Dn.rank = temps.get<uint32_t>(n);
         const size_t nbL = (size_t)1 << (3 * L);
         P.run(K_ZERO, (double)nbL * 4, [&] { launch_zero(Dn.bin[L], nbL * 4, st); });
-        P.run(K_DENSE, (double)n * (12 + 8), [&] {
+        P.run(K_DCOUNT, (double)n * (12 + 8), [&] {
           launch_dense_count(S.xyz, n, L, Dn.bin[L], Dn.key, Dn.rank, &meta->err_range, st);
         });
         for (int l = (int)L - 1; l >= 0; --l)
-          P.run(K_DENSE, (double)(1u << (3 * l)) * 36, [&] {
+          P.run(K_DSCAN, (double)(1u << (3 * l)) * 36, [&] {
             launch_dense_reduce(Dn.bin[l + 1], 1u << (3 * l), Dn.bin[l], st);
           });
         for (uint32_t l = 0; l <= L; ++l) {
           const uint32_t nb = 1u << (3 * l);
           uint64_t* stw = sa.take_words(dense_scan_tiles(nb));
           uint32_t* tk = sa.take_ticket();
-          P.run(K_DENSE, (double)nb * 12, [&] {
+          P.run(K_DSCAN, (double)nb * 12, [&] {
             launch_dense_scan(key64, Dn.bin[l], nb, Dn.sbin[l], Dn.srank[l], S.lv[l].key,
                               S.lv[l].begin, &meta->n_boxes[s][l], &meta->max_occ[s][l], stw, tk,
                               st);
           });
         }
         for (uint32_t l = 0; l < L; ++l)
-          P.run(K_DENSE, 0.0, [&] {
+          P.run(K_DSCAN, 0.0, [&] {
             launch_dense_links(key64, S.lv[l].key, &meta->n_boxes[s][l], S.lv[l].cap,
                                Dn.bin[l + 1], Dn.srank[l + 1], &meta->n_boxes[s][l + 1],
                                S.lv[l].child, S.lv[l].mask, S.lv[l + 1].key, S.lv[l + 1].cap,
@@ -766,7 +767,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       if (hm->max_occ[s][L] <= kDenseCanonMax) {
         uint32_t* tmp = temps.get<uint32_t>(n);
         uint32_t* big = temps.get<uint32_t>(std::max<uint32_t>(nb[s][L], 1));
-        P.run(K_DENSE, (double)n * (8 + 4 + 4 + 4 + 4 + 4 + 12 + 12), [&] {
+        P.run(K_DORDER, (double)n * (8 + 4 + 4 + 4 + 4 + 4 + 12 + 12), [&] {
           launch_dense_order(dn[s].key, dn[s].rank, n, dn[s].sbin[L], S.lv[L].begin,
                              &meta->n_boxes[s][L], nb[s][L], tmp, S.perm, big,
                              &meta->dense_big[s], S.xyz, S.sorted_xyz, st);
@@ -840,8 +841,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
       // level 2 only: the fill of each level writes the next level's counts
       if (dense)
-        P.run(K_DENSE, 0.0, [&] {
-          launch_dense_lists(key64, false, l, nr, sets[rs].lv[l].key, dn[0].bin[l - 1],
+        P.run(K_DLIST, 0.0, [&] {
+          launch_dense_lists(key64, false, l, nb[rs][l - 1], sets[rs].lv[l - 1].key,
+                             sets[rs].lv[l - 1].mask, sets[rs].lv[l - 1].child, dn[0].bin[l - 1],
                              dn[0].bin[l], dn[0].srank[l], cnt, cnt + round_up(nr, 4), nullptr,
                              nullptr, nullptr, nullptr, st);
         });
@@ -866,8 +868,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
       }
       if (dense) {
-        P.run(K_DENSE, 0.0, [&] {
-          launch_dense_lists(key64, true, l, nr, sets[rs].lv[l].key, dn[0].bin[l - 1],
+        P.run(K_DLIST, 0.0, [&] {
+          launch_dense_lists(key64, true, l, nb[rs][l - 1], sets[rs].lv[l - 1].key,
+                             sets[rs].lv[l - 1].mask, sets[rs].lv[l - 1].child, dn[0].bin[l - 1],
                              dn[0].bin[l], dn[0].srank[l], nullptr, nullptr, LB.off[0],
                              LB.off[1], LB.ent[0], LB.ent[1], st);
         });
