@@ -298,6 +298,19 @@ uint32_t level_cap(uint32_t n, uint32_t l) {
   return (uint32_t)std::min<uint64_t>(n, boxes);
 }
 
+// A second stream per device (default priority, created once, kept until
+// the process ends) for the receiver chain of a build.
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  ck(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Fail{FMMDS_ERR_DEVICE};
+  std::lock_guard<std::mutex> g(mu);
+  if (!streams[dev]) ck(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
+}
+
 // Host copy of the metadata block, through a pinned buffer of this thread.
 DevMeta* host_meta() {
   thread_local DevMeta* h = nullptr;
@@ -508,6 +521,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     P.run(K_ZERO, (double)ws_b, [&] { launch_zero(ws, ws_b, st); });
     const uint32_t n_max = std::max(sets[0].n, sets[nsets - 1].n);
     SortBufs sb{};
+    SortBufs& sb0 = sb;
     sb.k[0] = temps.get<uint64_t>(n_max);
     sb.k[1] = temps.get<uint64_t>(n_max);
     if (!packed || prev) {
@@ -576,6 +590,20 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       uint32_t* rank = nullptr;
     } dn[2];
 
+    // Separate source and receiver sets of a plain build are independent
+    // until the lists: the receivers' chain runs on a second stream, so that
+    // the latency-bound kernels of the two chains overlap. Every buffer is
+    // taken before the chains start (the allocator orders blocks on `st`).
+    const bool two = nsets == 2 && !dense && !prev;
+    SortBufs sb1 = sb;
+    if (two) {
+      sb1.k[0] = temps.get<uint64_t>(n_max);
+      sb1.k[1] = temps.get<uint64_t>(n_max);
+      if (!packed) {
+        sb1.v[0] = temps.get<uint32_t>(n_max);
+        sb1.v[1] = temps.get<uint32_t>(n_max);
+      }
+    }
     for (int s = 0; s < nsets; ++s) {
       SetBufs& S = sets[s];
       const uint32_t n = S.n;
@@ -609,6 +637,21 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           tp += round_up(c, 256);
         }
       }
+    }
+    hipStream_t st1 = st;
+    if (two) {
+      st1 = side_stream();
+      EventRef e0 = record_event(st);
+      if (e0->ev) ck(hipStreamWaitEvent(st1, e0->ev, 0));
+    }
+
+    for (int s = 0; s < nsets; ++s) {
+      SetBufs& S = sets[s];
+      const uint32_t n = S.n;
+      // this set's chain: its stream, and the profiler's events on it
+      const hipStream_t st = s == 1 ? st1 : impl->A.stream;
+      P.s = st;
+      SortBufs& sb = s == 1 ? sb1 : sb0;
 
       if (dense) {
         // Algorithm 1 at level L, the counters of the coarser levels, then
@@ -738,6 +781,12 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           }, s, (int)l);
         }
       }
+    }
+
+    P.s = st;
+    if (two) {
+      EventRef e1 = record_event(st1);
+      if (e1->ev) ck(hipStreamWaitEvent(st, e1->ev, 0));
     }
 
     // ---- sync point 1: box counts, range flag, occupancy maxima
@@ -934,6 +983,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     result = FMMDS_ERR_NOMEM;
   }
   if (result != FMMDS_OK) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();  // a second stream may still use the buffers
     (void)hipGetLastError();
     P.drop();
     temps.release_all();

@@ -130,7 +130,10 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
   // unconditional and all in flight at once (results past n_in are
   // discarded); every load precedes every store, since on this GPU a wait
   // for a load also waits for all earlier stores.
-  uint64_t kv[kCompItems], kp[kCompItems];
+  // Lanes 0..7 also load the 8 keys after the wave's last box (a parent's
+  // run of children may continue there).
+  const uint32_t lane = tid & 63u;
+  uint64_t kv[kCompItems], kp[kCompItems], kn[kCompItems];
   uint32_t bfirst[kCompItems];
 #pragma unroll
   for (int i = 0; i < kCompItems; ++i) {
@@ -138,12 +141,14 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
     kv[i] = (uint64_t)kin[jc];
     kp[i] = (uint64_t)kin[jc > 0 ? jc - 1 : 0];
     bfirst[i] = bin[jc];
+    const uint64_t wend = tbase + (uint64_t)i * kCompBlock + (tid & ~63u) + 64;
+    const uint64_t jn = min<uint64_t>(wend + lane, n_in - 1);
+    kn[i] = lane < 8 ? (uint64_t)kin[jn] : 0;
   }
   uint64_t pkey[kCompItems];
   uint32_t incl[kCompItems];
   uint32_t cmask[kCompItems];  // child octants of the parent a flagged box starts
   uint32_t flags = 0;
-  const uint32_t lane = tid & 63u;
 #pragma unroll
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t j = tbase + (uint64_t)i * kCompBlock + tid;
@@ -165,13 +170,13 @@ __global__ __launch_bounds__(kCompBlock) void k_level(
     uint32_t m = 0;
 #pragma unroll
     for (uint32_t b = 0; b < 8; ++b) m |= ((__ballot(oct == b) & run) ? 1u : 0u) << b;
-    if (f && end == 64) {
-      // the run may continue past this wave's last lane
-      for (uint64_t t = j + (64 - lane); t < n_in && t < j + 8; ++t) {
-        const uint64_t kt = (uint64_t)kin[t];
-        if ((kt >> 3) != pk) break;
-        m |= 1u << (kt & 7u);
-      }
+    // The run may continue past this wave's last lane, over at most the 8
+    // boxes loaded above (keys ascend, so the run is a prefix of them).
+    const uint64_t wend = j + (64 - lane);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const uint64_t kt = __shfl(kn[i], t, 64);
+      if (f && end == 64 && wend + t < n_in && (kt >> 3) == pk) m |= 1u << (kt & 7u);
     }
     cmask[i] = m;
   }
