@@ -594,16 +594,25 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // until the lists: the receivers' chain runs on a second stream, so that
     // the latency-bound kernels of the two chains overlap. Every buffer is
     // taken before the chains start (the allocator orders blocks on `st`).
-    const bool two = nsets == 2 && !dense && !prev;
+    const bool two = nsets == 2 && !dense;
     SortBufs sb1 = sb;
+    uint64_t* inc_fks[2] = {inc_fk, inc_fk};  // incremental: merged pairs per set
+    uint32_t* inc_fvs[2] = {inc_fv, inc_fv};
+    float* full_x[2] = {nullptr, nullptr};    // incremental fallback: original order
     if (two) {
       sb1.k[0] = temps.get<uint64_t>(n_max);
       sb1.k[1] = temps.get<uint64_t>(n_max);
-      if (!packed) {
+      if (!packed || prev) {
         sb1.v[0] = temps.get<uint32_t>(n_max);
         sb1.v[1] = temps.get<uint32_t>(n_max);
       }
+      if (prev) {
+        inc_fks[1] = temps.get<uint64_t>(n_max);
+        inc_fvs[1] = temps.get<uint32_t>(n_max);
+      }
     }
+    for (int s = 0; s < nsets; ++s)
+      if (prev && prev_order && !inc[s]) full_x[s] = temps.get<float>(3 * (size_t)sets[s].n);
     for (int s = 0; s < nsets; ++s) {
       SetBufs& S = sets[s];
       const uint32_t n = S.n;
@@ -703,8 +712,10 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       if (inc[s]) {
         // The movers sorted by (key, index), then merged with the stayers.
         const uint32_t ib = ibits[s], np = inc_pass[s], nm = n_move[s];
-        uint64_t* mk[2] = {inc_mv[s], s == 0 ? sb.k[1] : temps.get<uint64_t>(n)};
-        uint32_t* mv[2] = {inc_ms[s], s == 0 ? sb.v[1] : temps.get<uint32_t>(n)};
+        uint64_t* mk[2] = {inc_mv[s], sb.k[1]};
+        uint32_t* mv[2] = {inc_ms[s], sb.v[1]};
+        uint64_t* inc_fk = inc_fks[s];
+        uint32_t* inc_fv = inc_fvs[s];
         P.run(K_DIGITS, (double)np * 2048, [&] { launch_digit_offsets(h, g, np, st); });
         for (uint32_t p = 0; p < np && nm > 0; ++p) {
           const int a = p & 1, b = a ^ 1;
@@ -727,7 +738,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       } else {
         if (prev && prev_order) {
           // the merge value does not fit: full sort, from original order
-          float* x = temps.get<float>(3 * (size_t)n);
+          float* x = full_x[s];
           P.run(K_PLACE, 0.0, [&] { launch_inc_scatter(S.xyz, old_perm[s], n, x, st); });
           S.xyz = x;
           leaf_xyz = x;
