@@ -226,6 +226,7 @@ void launch_pack_sources(const float* sxyz, const uint32_t* sperm, const float* 
 void launch_near_field(uint32_t n_recv, uint32_t n_rbox, const uint32_t* rbegin,
                        const float* rxyz, const uint32_t* rperm, const uint32_t* e2_off,
                        const uint32_t* e2_ent, const uint32_t* sbegin, const float4* src,
-                       float* phi, unsigned long long* n_pairs, hipStream_t s);
+                       float* phi, unsigned long long* n_pairs, uint32_t* box_of,
+                       hipStream_t s);  // box_of: n_recv scratch entries
 
 }  // namespace fmmds
