@@ -187,3 +187,26 @@ def test_full_uniform_2x2p24_L8_equals_fresh_build(F):
         g.free()
     prev.free()
     fresh.free()
+
+
+def test_rebuild_from_a_batch_set(F, oracle_lib):
+    """A set of a batch is a tree too: rebuilding from it gives the tree a
+    plain build of the moved points gives."""
+    import torch
+    sizes = [6000, 3000]
+    pts = [I.sphere_cluster_points(260 + i, 261, n) for i, n in enumerate(sizes)]
+    lev = np.asarray([6, 5], np.uint8)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = F.Batch(off, lev)
+    b.launch(parity.to_gpu(np.concatenate(pts)))
+    b.wait()
+    for i in range(2):
+        moved = I.moved_points(pts[i], 270 + i, 3e-4)
+        g = F.rebuild(b.tree(i), parity.to_gpu(moved), None)
+        torch.cuda.synchronize()
+        o = oracle_lib.OracleTree(moved, None, key_bits=64, max_level=int(lev[i]))
+        parity.compare_tables(g, o, 64)
+        parity.compare_lists(g, o)
+        g.free()
+        o.close()
+    b.free()
