@@ -159,14 +159,27 @@ def kernel_stats_summary(stats_csv: str, out: str, workload_name: str):
              "```", cmd, f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
              f"{os.path.relpath(out, ROOT)} --workload {workload_name}", "```", "",
              "Every dispatch of the run (calibration, warm-up and timed builds alike; all have the "
-             "same shape). Averages are per dispatch, over every level of both point sets.", "",
+             "same shape). Averages are per dispatch, over every level of both point sets. The "
+             "source and receiver chains of a build run on two streams until the lists, so the "
+             "front kernels' durations include time shared with the other chain.", "",
              "| kernel | calls | avg (us) | min (us) | max (us) | share |",
              "|---|---:|---:|---:|---:|---:|"]
+    by_class = {}
     for r in rows:
         short = r["Name"].split("(")[0].replace("void ", "")
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f}% |")
+        cls = _kernel_class(r["Name"])
+        if cls:
+            c = by_class.setdefault(cls, [0, 0.0])
+            c[0] += int(r["Calls"])
+            c[1] += float(r["TotalDurationNs"]) / 1e3
+    lines += ["", "Per kernel class (the classes `bench.py` times with HIP events; template "
+              "instances of one kernel together):", "",
+              "| class | calls | avg (us) |", "|---|---:|---:|"]
+    for cls, (calls, tot) in sorted(by_class.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{cls}` | {calls} | {tot / calls:.1f} |")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
