@@ -118,7 +118,12 @@ typedef struct fmmds_tree {
  *   opt:      host, required.
  *   out:      host; receives a tree owned by the library.
  * Synchronous: when it returns FMMDS_OK every output is complete and visible
- * to work later enqueued on opt->stream. Inputs are not retained.
+ * to work later enqueued on opt->stream. Inputs are not retained. With
+ * separate receivers, the receivers' sort and tables run on a library-owned
+ * stream of the current device (default priority, created on first use and
+ * kept until the process ends) and are joined to opt->stream before the
+ * lists; the call waits on the host for box counts and list sizes, so it
+ * cannot be captured into a graph (the batched form can).
  */
 fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
                          uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
