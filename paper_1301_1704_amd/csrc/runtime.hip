@@ -590,11 +590,11 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       uint32_t* rank = nullptr;
     } dn[2];
 
-    // Separate source and receiver sets of a plain build are independent
-    // until the lists: the receivers' chain runs on a second stream, so that
-    // the latency-bound kernels of the two chains overlap. Every buffer is
-    // taken before the chains start (the allocator orders blocks on `st`).
-    const bool two = nsets == 2 && !dense;
+    // Separate source and receiver sets are independent until the lists: the
+    // receivers' chain runs on a second stream, so that the latency-bound
+    // kernels of the two chains overlap. Every buffer is taken before the
+    // chains start (the allocator orders blocks on `st`).
+    const bool two = nsets == 2;
     SortBufs sb1 = sb;
     uint64_t* inc_fks[2] = {inc_fk, inc_fk};  // incremental: merged pairs per set
     uint32_t* inc_fvs[2] = {inc_fv, inc_fv};
@@ -647,6 +647,17 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         }
       }
     }
+    for (int s = 0; dense && s < nsets; ++s) {
+      DenseSet& Dn = dn[s];
+      for (uint32_t l = 0; l <= L; ++l) {
+        const size_t nb = (size_t)1 << (3 * l);
+        Dn.bin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+        Dn.sbin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+        Dn.srank[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
+      }
+      Dn.key = temps.get<uint32_t>(sets[s].n);
+      Dn.rank = temps.get<uint32_t>(sets[s].n);
+    }
     hipStream_t st1 = st;
     if (two) {
       st1 = side_stream();
@@ -666,14 +677,6 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         // Algorithm 1 at level L, the counters of the coarser levels, then
         // Algorithm 3 per level and the parent / child links.
         DenseSet& Dn = dn[s];
-        for (uint32_t l = 0; l <= L; ++l) {
-          const size_t nb = (size_t)1 << (3 * l);
-          Dn.bin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
-          Dn.sbin[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
-          Dn.srank[l] = temps.get<uint32_t>(std::max<size_t>(nb, 8));
-        }
-        Dn.key = temps.get<uint32_t>(n);
-        Dn.rank = temps.get<uint32_t>(n);
         const size_t nbL = (size_t)1 << (3 * L);
         P.run(K_ZERO, (double)nbL * 4, [&] { launch_zero(Dn.bin[L], nbL * 4, st); });
         P.run(K_DCOUNT, (double)n * (12 + 8), [&] {
