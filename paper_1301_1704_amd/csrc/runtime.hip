@@ -355,6 +355,8 @@ std::mutex g_prof_mu;
 ClassStat g_prof[K_NCLASS];
 std::vector<hipEvent_t> g_events;  // reusable, guarded by g_prof_mu
 
+constexpr int kListSet = 2;  // Prof record tag: a list fill of level `level`
+
 struct Prof {
   bool on = false;
   hipStream_t s = nullptr;
@@ -878,6 +880,17 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     P.run(K_ZERO, (double)lws_b, [&] { launch_zero(lws, lws_b, st); });
     // E2 counts, then E4 counts from a 16-byte aligned start (vector loads)
     uint32_t* cnt = temps.get<uint32_t>(2 * round_up(std::max<size_t>(lmax, 1), 4));
+    // Levels much smaller than the finest get their entries allocated for
+    // the worst case (27 E2 and 189 E4 per receiver box) and need no host
+    // round trip for their totals, which are read at the next one; the large
+    // levels are allocated exactly.
+    auto small_level = [&](uint32_t l) {
+      return l < D && (uint64_t)nb[rs][l] * 16 <= (uint64_t)nb[rs][D];
+    };
+    auto take_totals = [&](const DevMeta* h, uint32_t upto) {
+      for (uint32_t m = 2; m <= upto; ++m)
+        for (int k = 0; k < 2; ++k) impl->lists[m].total[k] = h->list_total[k][m];
+    };
     for (uint32_t l = 2; l <= D; ++l) {
       const uint32_t nr = nb[rs][l];
       ListLevelArgs a{};
@@ -898,9 +911,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       }
       ListBufs& LB = impl->lists[l];
       // receiver key + parent in, two counts out; the parent lists and the
-      // parent-level source keys, masks and first children read once
-      const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
-      const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) + e2up * 4 +
+      // parent-level source keys, masks and first children read once (the
+      // list sizes are added once known, see P.finish below)
+      const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) +
                           (double)nb[0][l - 1] * (ksz + 1 + 4);
       // level 2 only: the fill of each level writes the next level's counts
       if (dense)
@@ -924,11 +937,14 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
                               &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st);
         });
       }
-      fetch_meta(meta, hm, st);  // sync point: this level's list totals
-      if (hm->overflow) throw Fail{FMMDS_ERR_OVERFLOW};
-      for (int k = 0; k < 2; ++k) {
-        LB.total[k] = hm->list_total[k][l];
-        LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
+      if (small_level(l)) {
+        for (int k = 0; k < 2; ++k)
+          LB.ent[k] = impl->outs.get<uint32_t>((size_t)nr * (k == 0 ? 27 : 189));
+      } else {
+        fetch_meta(meta, hm, st);  // sync point: this level's list totals
+        if (hm->overflow) throw Fail{FMMDS_ERR_OVERFLOW};
+        take_totals(hm, l);
+        for (int k = 0; k < 2; ++k) LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
       }
       if (dense) {
         P.run(K_DLIST, 0.0, [&] {
@@ -949,8 +965,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         a.cnt4_next = cnt + round_up(nb[rs][l + 1], 4);
         next_b = (double)nr * 5 + (double)nb[0][l] + (double)nb[rs][l + 1] * 8;
       }
-      P.run(K_FILL, side + (double)nr * 8 + 4.0 * (double)(LB.total[0] + LB.total[1]) + next_b,
-            [&] { launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st); });
+      P.run(K_FILL, side + (double)nr * 8 + next_b,
+            [&] { launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st); },
+            kListSet, (int)l);
       impl->n_recv_boxes[l] = nr;
     }
 
@@ -958,6 +975,11 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // the finer keys and bookmarks and writes keys, bookmarks, first children,
     // masks and the finer level's parents; the occupancy pass reads bookmarks.
     P.finish([&](const Prof::Rec& r) -> double {
+      if (r.set == kListSet) {  // a fill: its entries, and the parent level's E2 list read
+        const ListBufs& LB = impl->lists[r.level];
+        const double e2up = r.level - 1 >= 2 ? (double)impl->lists[r.level - 1].total[0] : 0.0;
+        return 4.0 * (double)(LB.total[0] + LB.total[1]) + 4.0 * e2up;
+      }
       if (r.set < 0) return 0.0;
       const uint32_t* c = nb[r.set == 0 ? 0 : rs];
       if (r.cls == K_LEAF) return (double)c[r.level] * (ksz + 4);
