@@ -880,12 +880,12 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     P.run(K_ZERO, (double)lws_b, [&] { launch_zero(lws, lws_b, st); });
     // E2 counts, then E4 counts from a 16-byte aligned start (vector loads)
     uint32_t* cnt = temps.get<uint32_t>(2 * round_up(std::max<size_t>(lmax, 1), 4));
-    // Levels much smaller than the finest get their entries allocated for
-    // the worst case (27 E2 and 189 E4 per receiver box) and need no host
-    // round trip for their totals, which are read at the next one; the large
-    // levels are allocated exactly.
+    // Levels with at most a quarter of the finest level's receiver boxes get
+    // their entries allocated for the worst case (27 E2 and 189 E4 per
+    // receiver box) and need no host round trip for their totals, which are
+    // read at the next one; the finest level is allocated exactly.
     auto small_level = [&](uint32_t l) {
-      return l < D && (uint64_t)nb[rs][l] * 16 <= (uint64_t)nb[rs][D];
+      return l < D && (uint64_t)nb[rs][l] * 4 <= (uint64_t)nb[rs][D];
     };
     auto take_totals = [&](const DevMeta* h, uint32_t upto) {
       for (uint32_t m = 2; m <= upto; ++m)
