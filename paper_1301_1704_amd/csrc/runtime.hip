@@ -667,6 +667,23 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       if (e0->ev) ck(hipStreamWaitEvent(st1, e0->ev, 0));
     }
 
+    // Plain builds: both chains' key generation is enqueued first, so that
+    // the receivers' chain starts while the host enqueues the rest.
+    const bool plain = !dense && !prev;
+    for (int s = 0; plain && s < nsets; ++s) {
+      const hipStream_t st = s == 1 ? st1 : impl->A.stream;
+      P.s = st;
+      SortBufs& sb = s == 1 ? sb1 : sb0;
+      const uint32_t n = sets[s].n;
+      uint32_t* h = hist + s * kMaxPasses * 256;
+      uint32_t* g = goff + s * kMaxPasses * 256;
+      P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
+        launch_keygen(sets[s].xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range,
+                      st);
+      });
+      P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+    }
+
     for (int s = 0; s < nsets; ++s) {
       SetBufs& S = sets[s];
       const uint32_t n = S.n;
@@ -748,10 +765,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           S.xyz = x;
           leaf_xyz = x;
         }
-        P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
-          launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
-        });
-        P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+        if (!plain) {  // (plain builds enqueued these above)
+          P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
+            launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range,
+                          st);
+          });
+          P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+        }
         for (uint32_t p = 0; p < n_pass; ++p) {
           const int a = p & 1, b = a ^ 1;
           const uint32_t shift = (packed ? 32 : 0) + 8 * p;
