@@ -169,7 +169,8 @@ __device__ __forceinline__ void place_one(uint64_t x, uint32_t s, uint64_t pos, 
   sorted_xyz[pos] = p;
 }
 
-// The few movers: a binary search over all stayers each.
+// Movers against a whole stayer list, a binary search each (the runtime
+// uses it when no point stayed: the sorted movers are then the order).
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_inc_place_movers(
     const uint64_t* __restrict__ v, const uint32_t* __restrict__ slot, uint32_t cnt,
