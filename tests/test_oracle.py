@@ -449,3 +449,32 @@ def test_near_field_one_point_agrees(oracle_lib):
         f1, a1 = t.near_field_one(j, q)
         assert f1 == pytest.approx(phi[j], rel=1e-12, abs=1e-12 * a[j])
         assert a1 == pytest.approx(a[j], rel=1e-12)
+
+
+def test_order_after_a_move_is_a_merge(oracle_lib):
+    """The premise of the incremental rebuild, on the oracle alone: after the
+    points move, the points that stayed in their finest box keep their
+    relative order, so the new order is the merge of that old subsequence
+    with the movers sorted by (key, index)."""
+    from paper_1301_1704_amd import inputs as I
+    L = 6
+    p = I.sphere_cluster_points(501, 502, 20000)
+    q = I.moved_points(p, 503, 2e-3)
+    a = oracle_lib.OracleTree(p, None, key_bits=64, max_level=L, with_lists=False)
+    b = oracle_lib.OracleTree(q, None, key_bits=64, max_level=L, with_lists=False)
+    old_perm, new_perm = a.perm(0).astype(np.int64), b.perm(0).astype(np.int64)
+    old_key = np.empty(p.shape[0], np.uint64)
+    new_key = np.empty(p.shape[0], np.uint64)
+    # every point's finest key, from each tree's boxes and bookmarks
+    for tree, perm, out in ((a, old_perm, old_key), (b, new_perm, new_key)):
+        keys, begin = tree.keys(0, L), tree.begin(0, L).astype(np.int64)
+        out[perm] = np.repeat(keys, np.diff(begin))
+    stay = old_key == new_key
+    assert 0 < stay.sum() < p.shape[0]
+    # stayers: same relative order in both
+    assert np.array_equal(old_perm[stay[old_perm]], new_perm[stay[new_perm]])
+    # the whole new order is (key, index) ascending, so it is the merge
+    k = new_key[new_perm]
+    assert np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (new_perm[1:] > new_perm[:-1])))
+    a.close()
+    b.close()
