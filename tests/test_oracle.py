@@ -478,3 +478,33 @@ def test_order_after_a_move_is_a_merge(oracle_lib):
     assert np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (new_perm[1:] > new_perm[:-1])))
     a.close()
     b.close()
+
+
+def test_dense_histogram_scans_give_the_tables(oracle_lib):
+    """Algorithm 3 written out with numpy on the dense occupancy histogram of
+    every level (reading c6: bookmark = exclusive scan of Bin, rank =
+    inclusive scan of the nonempty flags minus one) equals the oracle's
+    compacted tables, and the parent rank is ScannedRank of the key >> 3."""
+    from paper_1301_1704_amd import inputs as I
+    L = 6
+    p = I.sphere_cluster_points(511, 512, 30000)
+    o = oracle_lib.OracleTree(p, None, key_bits=64, max_level=L, with_lists=False)
+    perm = o.perm(0).astype(np.int64)
+    keys_L, begin_L = o.keys(0, L), o.begin(0, L).astype(np.int64)
+    point_key = np.empty(p.shape[0], np.uint64)
+    point_key[perm] = np.repeat(keys_L, np.diff(begin_L))
+    for l in range(L + 1):
+        k = (point_key >> np.uint64(3 * (L - l))).astype(np.int64)
+        bins = np.bincount(k, minlength=8 ** l)
+        scanned_bin = np.concatenate([[0], np.cumsum(bins)])
+        flags = bins > 0
+        scanned_rank = np.cumsum(flags) - 1
+        nonempty = np.nonzero(flags)[0]
+        assert np.array_equal(o.keys(0, l).astype(np.int64), nonempty)
+        assert np.array_equal(o.begin(0, l).astype(np.int64),
+                              np.concatenate([scanned_bin[nonempty], [p.shape[0]]]))
+        if l >= 1:
+            assert np.array_equal(o.parent(0, l).astype(np.int64),
+                                  prev_rank[nonempty >> 3])
+        prev_rank = scanned_rank
+    o.close()
