@@ -223,10 +223,9 @@ void launch_types_deep(bool key64, const BoxTypeLevel& a, hipStream_t s);
 // ---- nearfield.hip
 void launch_pack_sources(const float* sxyz, const uint32_t* sperm, const float* charges,
                          uint32_t n, float4* out, hipStream_t s);
-void launch_near_field(uint32_t n_recv, uint32_t n_rbox, const uint32_t* rbegin,
-                       const float* rxyz, const uint32_t* rperm, const uint32_t* e2_off,
-                       const uint32_t* e2_ent, const uint32_t* sbegin, const float4* src,
-                       float* phi, unsigned long long* n_pairs, uint32_t* box_of,
-                       hipStream_t s);  // box_of: n_recv scratch entries
+void launch_near_field(uint32_t n_rbox, const uint32_t* rbegin, const float* rxyz,
+                       const uint32_t* rperm, const uint32_t* e2_off, const uint32_t* e2_ent,
+                       const uint32_t* sbegin, const float4* src, float* phi,
+                       unsigned long long* n_pairs, hipStream_t s);
 
 }  // namespace fmmds

@@ -11,9 +11,9 @@
 //
 // Layout: the sorted source points and their charges are packed once into
 // 16-byte records (x, y, z, q), so each source point is one 16-byte load.
-// One thread per receiver point in sorted order (its box from a point-to-box
-// map): the lanes of a wave sit in neighboring boxes with overlapping E2
-// lists, so most source loads are shared through the caches.
+// One thread per receiver box: its points share every source load, and the
+// lanes of a wave sit in neighboring boxes with overlapping E2 lists, so most
+// of those loads are shared through the caches too.
 #include "device.h"
 #include "internal.h"
 
@@ -29,67 +29,65 @@ __global__ __launch_bounds__(256) void k_pack_sources(const float* __restrict__ 
   }
 }
 
-// The finest receiver box of every sorted receiver point (a thread per box
-// writes its points' entries), so that the sum needs no search.
-__global__ __launch_bounds__(256) void k_point_box(const uint32_t* __restrict__ rbegin,
-                                                   uint32_t n_rbox, uint32_t* __restrict__ box_of) {
-  for (uint64_t b = blockIdx.x * 256ull + threadIdx.x; b < n_rbox; b += gridDim.x * 256ull) {
-    const uint32_t k1 = rbegin[b + 1];
-    for (uint32_t k = rbegin[b]; k < k1; ++k) box_of[k] = (uint32_t)b;
-  }
-}
-
-// The list is walked eight entries at a time: their source ranks, then their
-// bookmarks, then their points (two loads in flight per step), so that the
-// dependent loads of eight entries overlap. The terms are added in list
-// order, point by point.
+// One thread per receiver box, up to kNearRecv of its points at a time: each
+// source point is loaded once for all of them. The list is walked eight
+// entries at a time (their source ranks, then their bookmarks, then their
+// points), so that the dependent loads of eight entries overlap. Every
+// receiver's terms are added in list order, point by point.
 constexpr uint32_t kNearBatch = 8;
+constexpr uint32_t kNearRecv = 4;
 
 __global__ __launch_bounds__(256) void k_near_field(
-    uint32_t n_recv, const uint32_t* __restrict__ box_of, const float* __restrict__ rxyz,
+    uint32_t n_rbox, const uint32_t* __restrict__ rbegin, const float* __restrict__ rxyz,
     const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ e2_off,
     const uint32_t* __restrict__ e2_ent, const uint32_t* __restrict__ sbegin,
     const float4* __restrict__ src, float* __restrict__ phi,
     unsigned long long* __restrict__ n_pairs) {
-  const uint64_t k = blockIdx.x * 256ull + threadIdx.x;
-  uint32_t pairs = 0;
-  if (k < n_recv) {
-    const uint32_t b = box_of[k];
-    const float yx = rxyz[3 * k], yy = rxyz[3 * k + 1], yz = rxyz[3 * k + 2];
-    float acc = 0.0f;
+  const uint64_t b = blockIdx.x * 256ull + threadIdx.x;
+  uint64_t pairs = 0;
+  if (b < n_rbox) {
+    const uint32_t k0 = rbegin[b], k1 = rbegin[b + 1];
     const uint32_t e0 = e2_off[b], e1 = e2_off[b + 1];
-    for (uint32_t e = e0; e < e1; e += kNearBatch) {
-      uint32_t sb[kNearBatch], i0[kNearBatch], i1[kNearBatch];
+    for (uint32_t kc = k0; kc < k1; kc += kNearRecv) {
+      float yx[kNearRecv], yy[kNearRecv], yz[kNearRecv], acc[kNearRecv];
 #pragma unroll
-      for (uint32_t j = 0; j < kNearBatch; ++j) sb[j] = e + j < e1 ? e2_ent[e + j] : 0u;
-#pragma unroll
-      for (uint32_t j = 0; j < kNearBatch; ++j) {
-        const bool ok = e + j < e1;
-        i0[j] = ok ? sbegin[sb[j]] : 0u;
-        i1[j] = ok ? sbegin[sb[j] + 1] : 0u;
+      for (uint32_t r = 0; r < kNearRecv; ++r) {
+        const uint32_t k = min(kc + r, k1 - 1);  // extra lanes repeat the last point
+        yx[r] = rxyz[3 * (uint64_t)k], yy[r] = rxyz[3 * (uint64_t)k + 1],
+        yz[r] = rxyz[3 * (uint64_t)k + 2];
+        acc[r] = 0.0f;
       }
+      uint32_t pts = 0;
+      for (uint32_t e = e0; e < e1; e += kNearBatch) {
+        uint32_t sb[kNearBatch], i0[kNearBatch], i1[kNearBatch];
 #pragma unroll
-      for (uint32_t j = 0; j < kNearBatch; ++j) {
-        uint32_t i = i0[j];
-        for (; i + 1 < i1[j]; i += 2) {
-          const float4 x = src[i], x2 = src[i + 1];
-          const float dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          acc += r2 > 0.0f ? x.w * rsqrtf(r2) : 0.0f;
-          const float ex = x2.x - yx, ey = x2.y - yy, ez = x2.z - yz;
-          const float s2 = ex * ex + ey * ey + ez * ez;
-          acc += s2 > 0.0f ? x2.w * rsqrtf(s2) : 0.0f;
+        for (uint32_t j = 0; j < kNearBatch; ++j) sb[j] = e + j < e1 ? e2_ent[e + j] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kNearBatch; ++j) {
+          const bool ok = e + j < e1;
+          i0[j] = ok ? sbegin[sb[j]] : 0u;
+          i1[j] = ok ? sbegin[sb[j] + 1] : 0u;
         }
-        if (i < i1[j]) {
-          const float4 x = src[i];
-          const float dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          acc += r2 > 0.0f ? x.w * rsqrtf(r2) : 0.0f;
+#pragma unroll
+        for (uint32_t j = 0; j < kNearBatch; ++j) {
+          for (uint32_t i = i0[j]; i < i1[j]; ++i) {
+            const float4 x = src[i];
+#pragma unroll
+            for (uint32_t r = 0; r < kNearRecv; ++r) {
+              const float dx = x.x - yx[r], dy = x.y - yy[r], dz = x.z - yz[r];
+              const float r2 = dx * dx + dy * dy + dz * dz;
+              acc[r] += r2 > 0.0f ? x.w * rsqrtf(r2) : 0.0f;
+            }
+          }
+          pts += i1[j] - i0[j];
         }
-        pairs += i1[j] - i0[j];
       }
+      const uint32_t nr = min(kNearRecv, k1 - kc);
+#pragma unroll
+      for (uint32_t r = 0; r < kNearRecv; ++r)
+        if (r < nr) phi[rperm[kc + r]] = acc[r];
+      pairs += (uint64_t)pts * nr;
     }
-    phi[rperm[k]] = acc;
   }
   if (n_pairs) {
     const uint64_t w = wave_sum_u64(pairs);
@@ -103,14 +101,12 @@ void launch_pack_sources(const float* sxyz, const uint32_t* sperm, const float* 
   hipLaunchKernelGGL(k_pack_sources, dim3(grid), dim3(256), 0, s, sxyz, sperm, charges, n, out);
 }
 
-void launch_near_field(uint32_t n_recv, uint32_t n_rbox, const uint32_t* rbegin,
-                       const float* rxyz, const uint32_t* rperm, const uint32_t* e2_off,
-                       const uint32_t* e2_ent, const uint32_t* sbegin, const float4* src,
-                       float* phi, unsigned long long* n_pairs, uint32_t* box_of,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_point_box, dim3(std::min<uint32_t>(div_up(n_rbox, 256), 8192)), dim3(256),
-                     0, s, rbegin, n_rbox, box_of);
-  hipLaunchKernelGGL(k_near_field, dim3(div_up(n_recv, 256)), dim3(256), 0, s, n_recv, box_of,
+void launch_near_field(uint32_t n_rbox, const uint32_t* rbegin, const float* rxyz,
+                       const uint32_t* rperm, const uint32_t* e2_off, const uint32_t* e2_ent,
+                       const uint32_t* sbegin, const float4* src, float* phi,
+                       unsigned long long* n_pairs, hipStream_t s) {
+  if (n_rbox == 0) return;
+  hipLaunchKernelGGL(k_near_field, dim3(div_up(n_rbox, 256)), dim3(256), 0, s, n_rbox, rbegin,
                      rxyz, rperm, e2_off, e2_ent, sbegin, src, phi, n_pairs);
 }
 

@@ -1706,14 +1706,12 @@ fmmds_status near_field(const fmmds_tree* t, const float* charges, float* phi,
   if (!t || !t->impl || !phi) return FMMDS_ERR_ARG;
   const TreeImpl* impl = (const TreeImpl*)t->impl;
   const uint32_t D = t->depth;
-  const size_t src_b = round_up((size_t)t->n_src * 16, 256);
-  void* src4 = cache_alloc(src_b + (size_t)t->n_recv * 4, st);
+  void* src4 = cache_alloc((size_t)t->n_src * 16, st);
   if (!src4) return FMMDS_ERR_NOMEM;
   launch_pack_sources(t->src_sorted_xyz, t->src_perm, charges, t->n_src, (float4*)src4, st);
-  launch_near_field(t->n_recv, t->recv[D].n, t->recv[D].begin, t->recv_sorted_xyz, t->recv_perm,
+  launch_near_field(t->recv[D].n, t->recv[D].begin, t->recv_sorted_xyz, t->recv_perm,
                     impl->lists[D].off[0], impl->lists[D].ent[0], t->src[D].begin,
-                    (const float4*)src4, phi, (unsigned long long*)n_pairs,
-                    (uint32_t*)((char*)src4 + src_b), st);
+                    (const float4*)src4, phi, (unsigned long long*)n_pairs, st);
   cache_release(src4, st);
   return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
 }
