@@ -497,7 +497,7 @@ def main():
         counter_summary(*args.counter_summary, args.workload)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent point sets shard trivially, one set spans one GPU)", file=sys.stderr)
         sys.exit(2)
 

@@ -149,7 +149,7 @@ fmmds_status fmmds_build_dense(const float* src_xyz, uint32_t n_src, const float
  * merged with the others, which are still in order. The result is exactly
  * the tree fmmds_build would return for the same positions and options.
  *   prev:     host; a tree from fmmds_build, fmmds_rebuild or a batch, with
- *             the point counts of this build; read only, and may be freed
+ *             the point counts of this call; read only, and may be freed
  *             once this call returns.
  *   src_xyz:  device, 3 * prev->n_src FP32 values. With in_prev_order == 0,
  *             row j is original point j (as for fmmds_build); with 1, row k
