@@ -82,8 +82,14 @@ COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving 
                 "--no-dense --no-profile --copy-calibration")
 
 
+def _short_name(name: str):
+    """Kernel name without its argument list (and without an anonymous
+    namespace, whose parentheses would cut it short)."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
+
+
 def _kernel_class(name: str):
-    base = name.split("(")[0].replace("void ", "").replace("fmmds::", "").strip()
+    base = _short_name(name).replace("fmmds::", "")
     for pat, cls in KERNEL_CLASS:
         if base == pat or base.split("<")[0] == pat:
             return cls
@@ -146,38 +152,51 @@ def counter_summary(fetch_csv: str, write_csv: str, out: str, workload_name: str
     print("\n".join(lines))
 
 
-def kernel_stats_summary(stats_csv: str, out: str, workload_name: str):
+BUILD_ONLY_FLAGS = "--no-cpu-baseline --no-batch --no-serving --no-rebuild --no-dense"
+
+
+def kernel_stats_summary(stats_csv: str, out: str, workload_name: str, flags=None):
     """Writes the per-kernel timing summary (profiles/) from the
     run_kernel_stats.csv of a rocprofv3 --kernel-trace --stats run of this
-    script."""
+    script. `flags`: the options of the profiled run when it was not the
+    plain build alone."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-           "-d <dir> -o run -- python3 <repo>/bench.py --workload " + workload_name +
-           " --no-cpu-baseline --no-batch --no-serving --no-rebuild --no-dense")
+           "-d <dir> -o run -- python3 <repo>/bench.py --workload " + workload_name + " " +
+           (flags or BUILD_ONLY_FLAGS))
+    again = (f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
+             f"{os.path.relpath(out, ROOT)} --workload {workload_name}")
+    if flags:
+        again += f" --profiled-flags '{flags}'"
+        note = ("Every dispatch of the run: the plain builds (warm-up and timed, and those the "
+                "rebuild and dense-variant measurements compare against), the near-field sum, "
+                "the partition and source box types, the incremental rebuilds and the "
+                "dense-histogram builds. Averages are per dispatch.")
+    else:
+        note = ("Every dispatch of the run (calibration, warm-up and timed builds alike; all have "
+                "the same shape). Averages are per dispatch, over every level of both point sets. "
+                "The source and receiver chains of a build run on two streams until the lists, so "
+                "the front kernels' durations include time shared with the other chain.")
     lines = [f"# Kernel times (rocprofv3 --kernel-trace --stats), workload `{workload_name}`", "",
-             "```", cmd, f"python3 bench.py --kernel-stats-summary <dir>/run_kernel_stats.csv "
-             f"{os.path.relpath(out, ROOT)} --workload {workload_name}", "```", "",
-             "Every dispatch of the run (calibration, warm-up and timed builds alike; all have the "
-             "same shape). Averages are per dispatch, over every level of both point sets. The "
-             "source and receiver chains of a build run on two streams until the lists, so the "
-             "front kernels' durations include time shared with the other chain.", "",
+             "```", cmd, again, "```", "", note, "",
              "| kernel | calls | avg (us) | min (us) | max (us) | share |",
              "|---|---:|---:|---:|---:|---:|"]
     by_class = {}
     for r in rows:
-        short = r["Name"].split("(")[0].replace("void ", "")
+        short = _short_name(r["Name"])
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f}% |")
-        cls = _kernel_class(r["Name"])
+        cls = None if flags else _kernel_class(r["Name"])
         if cls:
             c = by_class.setdefault(cls, [0, 0.0])
             c[0] += int(r["Calls"])
             c[1] += float(r["TotalDurationNs"]) / 1e3
-    lines += ["", "Per kernel class (the classes `bench.py` times with HIP events; template "
-              "instances of one kernel together):", "",
-              "| class | calls | avg (us) |", "|---|---:|---:|"]
+    if by_class:
+        lines += ["", "Per kernel class (the classes `bench.py` times with HIP events; template "
+                  "instances of one kernel together):", "",
+                  "| class | calls | avg (us) |", "|---|---:|---:|"]
     for cls, (calls, tot) in sorted(by_class.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"| `{cls}` | {calls} | {tot / calls:.1f} |")
     with open(out, "w") as fh:
@@ -489,9 +508,12 @@ def main():
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--kernel-stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
                     help="write the kernel timing summary from a rocprofv3 --stats run and exit")
+    ap.add_argument("--profiled-flags", default=None,
+                    help="with --kernel-stats-summary: the options of the profiled run, when it "
+                         "measured more than the plain build")
     args = ap.parse_args()
     if args.kernel_stats_summary:
-        kernel_stats_summary(*args.kernel_stats_summary, args.workload)
+        kernel_stats_summary(*args.kernel_stats_summary, args.workload, args.profiled_flags)
         return
     if args.counter_summary:
         counter_summary(*args.counter_summary, args.workload)
