@@ -122,8 +122,11 @@ typedef struct fmmds_tree {
  * separate receivers, the receivers' sort and tables run on a library-owned
  * stream of the current device (default priority, created on first use and
  * kept until the process ends) and are joined to opt->stream before the
- * lists; the call waits on the host for box counts and list sizes, so it
- * cannot be captured into a graph (the batched form can).
+ * lists. Concurrent calls on one device share that stream: their receiver
+ * chains run one after another there, each still ordered after its own
+ * caller's stream, so results are unaffected. The call waits on the host for
+ * box counts and list sizes, so it cannot be captured into a graph (the
+ * batched form can).
  */
 fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
                          uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
