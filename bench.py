@@ -169,10 +169,9 @@ def kernel_stats_summary(stats_csv: str, out: str, workload_name: str, flags=Non
              f"{os.path.relpath(out, ROOT)} --workload {workload_name}")
     if flags:
         again += f" --profiled-flags '{flags}'"
-        note = ("Every dispatch of the run: the plain builds (warm-up and timed, and those the "
-                "rebuild and dense-variant measurements compare against), the near-field sum, "
-                "the partition and source box types, the incremental rebuilds and the "
-                "dense-histogram builds. Averages are per dispatch.")
+        note = ("Every dispatch of the run: the plain builds (warm-up and timed, and those "
+                "other measurements compare against) and every measurement the options above "
+                "leave on. Averages are per dispatch.")
     else:
         note = ("Every dispatch of the run (calibration, warm-up and timed builds alike; all have "
                 "the same shape). Averages are per dispatch, over every level of both point sets. "
