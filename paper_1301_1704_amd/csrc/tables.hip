@@ -220,20 +220,42 @@ void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32
 // K8: largest box occupancy of a level (for the cluster-size depth rule,
 // Section 2.1).
 // ---------------------------------------------------------------------------
+// Each thread takes kOccItems consecutive boxes and loads their
+// kOccItems + 1 bookmarks at once (indices clamped to the sentinel at n_in,
+// which give 0), so a level is one round of loads rather than a loop of them.
+// The block's maximum goes out in one atomic: atomics on one address are
+// serialized, and one per wave made the largest levels slower.
+constexpr int kOccItems = 16;
+
 __global__ __launch_bounds__(256) void k_max_occupancy(const uint32_t* __restrict__ begin,
                                                        const uint32_t* __restrict__ n_in_p,
                                                        uint32_t* __restrict__ out) {
   const uint32_t n_in = *n_in_p;
+  const uint64_t j0 = ((uint64_t)blockIdx.x * 256u + threadIdx.x) * kOccItems;
   uint32_t m = 0;
-  for (uint64_t j = blockIdx.x * 256ull + threadIdx.x; j < n_in; j += gridDim.x * 256ull)
-    m = max(m, begin[j + 1] - begin[j]);
+  if (j0 < n_in) {
+    uint32_t b[kOccItems + 1];
+#pragma unroll
+    for (int i = 0; i <= kOccItems; ++i) {
+      const uint64_t j = j0 + (uint64_t)i;
+      b[i] = begin[j < n_in ? j : n_in];
+    }
+#pragma unroll
+    for (int i = 0; i < kOccItems; ++i) m = max(m, b[i + 1] - b[i]);
+  }
+  __shared__ uint32_t s_m[4];
   m = wave_max(m);
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+    if (m) atomicMax(out, m);
+  }
 }
 
 void launch_max_occupancy(const uint32_t* begin, const uint32_t* n_in, uint32_t cap,
                           uint32_t* out, hipStream_t s) {
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(div_up(cap, 256), 2048));
+  const uint32_t grid = std::max<uint32_t>(1, div_up(cap, 256u * kOccItems));
   hipLaunchKernelGGL(k_max_occupancy, dim3(grid), dim3(256), 0, s, begin, n_in, out);
 }
 
