@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void k_dense_scan(
   __shared__ uint64_t s_w[4];
   __shared__ uint64_t s_excl;
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_mx[4];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   __syncthreads();
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_dense_scan(
   }
   if (lane == 63) s_w[w] = inc;
   mx = wave_max(mx);
-  if (lane == 0 && mx) atomicMax(max_occ, mx);
+  if (lane == 0) s_mx[w] = mx;
   __syncthreads();
   uint64_t wpre = 0, tot = 0;
 #pragma unroll
@@ -145,6 +146,13 @@ __global__ __launch_bounds__(256) void k_dense_scan(
       begin[sr[k] + (c[k] > 0 ? 1u : 0u)] = sp[k] + c[k];
       *n_out = sr[k] + (c[k] > 0 ? 1u : 0u);
     }
+  }
+  // The level's largest occupancy: one atomic per block, after the look-back.
+  // Atomics on one address are serialized, and on this GPU the look-back's
+  // waits for its loads would also wait for an atomic issued before them.
+  if (tid == 0) {
+    const uint32_t m = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
+    if (m) atomicMax(max_occ, m);
   }
 }
 
