@@ -203,47 +203,128 @@ def kernel_stats_summary(stats_csv: str, out: str, workload_name: str, flags=Non
     print("\n".join(lines))
 
 
-def cpu_baseline(name: str):
-    """The oracle (single thread) on a bounded sample of the same workload:
-    1/8 of the points with one level less, i.e. the same points per box and
-    the same list lengths, on 1/8 of the boxes."""
+def cpu_model() -> str:
+    """CPU model name of this host (/proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_cores() -> int:
+    """Cores this process may use (the GPU machine gives one GPU 16 of them)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+class _Pinned:
+    """Runs the enclosed work on one core (sched_setaffinity), then restores
+    the previous affinity."""
+
+    def __enter__(self):
+        self.prev = os.sched_getaffinity(0)
+        self.core = min(self.prev)
+        os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *a):
+        os.sched_setaffinity(0, self.prev)
+
+
+def cpu_baseline(c, list_share: int = 16):
+    """The oracle, single-threaded and pinned to one core, on the benchmark's
+    own inputs: its tables of both sets whole (keys, sort, bookmarks, parents
+    and children of every level), and its E2 / E4 lists for one receiver box
+    in `list_share` of every level (evenly spaced ranges), scaled to all boxes.
+    Runs before the process first touches the GPU. The points/s figure is
+    (N + M) over the estimated whole-build time."""
     import oracle
-    from paper_1301_1704_amd import inputs as I
-    if name == "uniform":
-        n, L = 1 << 21, 7
-        src, recv, kb, s = I.uniform_points(2, n), I.uniform_points(3, n), 64, 0
-        desc = "2^21 + 2^21 uniform points, max level 7 (same density as 2^24 at level 8)"
-    elif name == "nonuniform":
-        n, L = 1 << 21, 9
-        src = I.sphere_cluster_points(5, 4, n)
-        recv = I.sphere_cluster_points(6, 4, n)
-        kb, s = 64, 64
-        desc = "2^21 + 2^21 sphere+cluster points, max level 9, s=64"
-    else:
-        c = I.config_plain_small()
-        src, recv, kb, s, L = c["src"], None, 32, 0, 5
-        n = src.shape[0]
-        desc = "the full 65,536-point workload"
     oracle.lib()
-    reps = 1 if name == "small" else 2  # about 15 s of single-thread work
+    src, recv = c["src"], c["recv"]
+    n_pts = src.shape[0] + (0 if recv is None else recv.shape[0])
+    with _Pinned() as pin:
+        t0 = time.perf_counter()
+        o = oracle.OracleTree(src, recv, key_bits=c["key_bits"], cluster_s=c["cluster_s"],
+                              max_level=c["max_level"], with_lists=False)
+        t_tables = time.perf_counter() - t0
+        t_lists, boxes, sampled = 0.0, 0, 0
+        for l in range(2, o.depth + 1):
+            nr = o.n_boxes(1, l)
+            t1 = time.perf_counter()
+            lk = o.lookup(l)
+            if nr < 64 * list_share:
+                ranges = [(0, nr)]
+            else:  # 64 ranges, together one box in list_share
+                step, width = nr // 64, max(1, nr // (64 * list_share))
+                ranges = [(k * step, k * step + width) for k in range(64)]
+            for r0, r1 in ranges:
+                for kind in (2, 4):
+                    lk.range(kind, r0, r1)
+            lk.close()
+            dt = time.perf_counter() - t1
+            part = sum(r1 - r0 for r0, r1 in ranges)
+            t_lists += dt * nr / part
+            boxes += nr
+            sampled += part
+        o.close()
+    est = t_tables + t_lists
+    return {"value": n_pts / est, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": (f"the benchmark's own inputs ({c['name']}): oracle tables of both sets "
+                       f"whole ({t_tables:.1f} s), E2/E4 lists of {sampled} of {boxes} receiver "
+                       f"boxes (levels 2..{o.depth}, 64 evenly spaced ranges per level) scaled "
+                       f"to all boxes ({t_lists:.1f} s estimated)"),
+            "seconds_estimated_build": round(est, 3), "seconds_run": round(time.perf_counter() - t0, 3),
+            "pinned_core": pin.core, "cpu": cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def _oracle_sets(job):
+    """Oracle builds (tables and lists) of a share of the batch's sets; runs in
+    a worker process."""
+    import oracle
+    xyz, off, lev, idx = job
     t0 = time.perf_counter()
-    for _ in range(reps):
-        t = oracle.OracleTree(src, recv, key_bits=kb, cluster_s=s, max_level=L, with_lists=True)
-        t.close()
-    dt = (time.perf_counter() - t0) / reps
-    pts = n if recv is None else 2 * n
-    return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{desc}; {reps} builds, mean time", "seconds": round(dt * reps, 3),
-            "cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+    for i in idx:
+        oracle.OracleTree(xyz[int(off[i]):int(off[i + 1])], None, key_bits=64,
+                          max_level=int(lev[i]), with_lists=True).close()
+    return time.perf_counter() - t0
 
 
-def bench_batched(F, torch, args):
+def cpu_baseline_batched(xyz, off, lev):
+    """The oracle over the batched workload's 512 sets, one worker process
+    per host core (forked before the process touches the GPU), sets dealt
+    largest first to the least loaded worker."""
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()
+    cores = host_cores()
+    sizes = np.diff(off.astype(np.int64))
+    shares = [[] for _ in range(cores)]
+    load = [0] * cores
+    for i in np.argsort(-sizes):
+        k = int(np.argmin(load))
+        shares[k].append(int(i))
+        load[k] += int(sizes[i])
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        busy = pool.map(_oracle_sets, [(xyz, off, lev, sh) for sh in shares])
+    wall = time.perf_counter() - t0
+    return {"value": len(lev) / wall, "unit": "builds/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {len(lev)} sets of the batched workload, tables and lists",
+            "seconds": round(wall, 3), "core_seconds": round(sum(busy), 3), "cpu": cpu_model()}
+
+
+def bench_batched(F, torch, args, sets):
     """Builds/sec of the batched form (512 sets of 2^10..2^20 points, one
     graph-replayed launch sequence) against the same 512 sets built one by
     one with fmmds_build on the same GPU and stream."""
-    from paper_1301_1704_amd import inputs as I
-    log("batched: generating 512 sets")
-    xyz, off, lev = I.batch_sets()
+    xyz, off, lev = sets
     x = torch.from_numpy(xyz).cuda()
     n_sets = len(lev)
     b = F.Batch(off, lev)
@@ -522,6 +603,26 @@ def main():
               "(independent point sets shard trivially, one set spans one GPU)", file=sys.stderr)
         sys.exit(2)
 
+    # Host-only work first: inputs, and the oracle legs, which run before the
+    # process first touches the GPU (the batched leg forks worker processes).
+    c = workload(args.workload)
+    log(f"workload {c['name']}: inputs generated")
+    batch_sets = None
+    if not args.no_batch:
+        from paper_1301_1704_amd import inputs as I
+        log("batched: generating 512 sets")
+        batch_sets = I.batch_sets()
+    cpu_line = cpu_batch = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: the oracle on the benchmark inputs, one pinned core")
+        cpu_line = cpu_baseline(c)
+        log(f"cpu baseline: {cpu_line['value']:.3g} points/s ({cpu_line['sample']})")
+        if batch_sets is not None:
+            log("cpu baseline: the oracle over the 512 batched sets, one process per core")
+            cpu_batch = cpu_baseline_batched(*batch_sets)
+            log(f"cpu baseline (batched): {cpu_batch['value']:.1f} builds/s on "
+                f"{cpu_batch['cores']} cores")
+
     import torch
     import paper_1301_1704_amd as F
 
@@ -535,8 +636,6 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    c = workload(args.workload)
-    log(f"workload {c['name']}: generating inputs")
     src = torch.from_numpy(c["src"]).cuda()
     recv = None if c["recv"] is None else torch.from_numpy(c["recv"]).cuda()
     n_pts = src.shape[0] + (0 if recv is None else recv.shape[0])
@@ -625,12 +724,13 @@ def main():
     if not args.no_dense and c["max_level"] <= 8:
         line["dense"] = bench_dense(F, torch, src, recv, kw)
     if not args.no_batch:
-        line["batched"] = bench_batched(F, torch, args)
+        line["batched"] = bench_batched(F, torch, args, batch_sets)
+        if cpu_batch is not None:
+            line["batched"]["cpu_baseline"] = cpu_batch
     if not args.no_serving:
         line["serving"] = bench_serving(F, torch, args)
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a sample")
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+    if cpu_line is not None:
+        line["cpu_baseline"] = cpu_line
     print(json.dumps(line), flush=True)
 
 

@@ -242,6 +242,21 @@ uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
 void fmmds_batch_free(fmmds_batch* b);
 
 /*
+ * The batched form in one call: plan, allocate, build and wait, i.e.
+ * fmmds_batch_create, one fmmds_batch_launch without graph capture and
+ * fmmds_batch_wait. Arguments as for those calls; xyz is device memory of
+ * set_offsets[n_sets] points. On FMMDS_OK *out holds the finished batch:
+ * fmmds_batch_tree gives the per-set views, fmmds_free_batch releases it (it
+ * may also be launched again like any batch). On error *out is NULL and
+ * nothing leaks.
+ */
+fmmds_status fmmds_build_batch(const float* xyz, const uint64_t* set_offsets,
+                               const uint8_t* levels, uint32_t n_sets, const fmmds_options* opt,
+                               fmmds_batch** out);
+/* Same as fmmds_batch_free. */
+void fmmds_free_batch(fmmds_batch* b);
+
+/*
  * Serving support: one time step of moving particle systems, for the
  * dynamic problems the paper motivates (Section 1, Section 2.5), so that a
  * rebuild request runs on the GPU from the step to the lists. Not a step of

@@ -64,6 +64,11 @@ def lib():
         L.oref_list_sizes.argtypes = [vp, i32, u32, C.POINTER(u32), C.POINTER(u64)]
         L.oref_list.argtypes = [vp, i32, u32, vp, vp]
         L.oref_box_list.argtypes = [vp, i32, u32, u32, vp]
+        L.oref_lookup_open.argtypes = [vp, u32]
+        L.oref_lookup_open.restype = vp
+        L.oref_lookup_close.argtypes = [vp]
+        L.oref_lookup_close.restype = None
+        L.oref_list_range.argtypes = [vp, i32, u32, u32, vp, vp]
         L.oref_partition.argtypes = [vp, u32, u32, vp]
         L.oref_box_types.argtypes = [vp, u32, vp, u32, vp]
         L.oref_box_type_one.argtypes = [vp, u32, vp, u32, u32, u32]
@@ -183,6 +188,10 @@ class OracleTree:
             raise OracleError(-n, "oref_box_list")
         return buf[:n].copy()
 
+    def lookup(self, level: int) -> "ListLookup":
+        """Range queries of the lists of one level (oref_list_range)."""
+        return ListLookup(self, level)
+
     def partition(self, l_par: int, n_ranks: int) -> np.ndarray:
         """Rank of every Morton index at level l_par (Section 3.2)."""
         out = np.empty(1 << (3 * l_par), dtype=np.uint32)
@@ -235,3 +244,33 @@ class OracleTree:
         if st != OK:
             raise OracleError(st, "oref_near_field_one")
         return f.value, a.value
+
+
+class ListLookup:
+    """E2 / E4 lists of ranges of receiver boxes of one level, computed from
+    the definition on demand. The oracle call releases the GIL, so several
+    Python threads can query one lookup at once."""
+
+    def __init__(self, tree: OracleTree, level: int):
+        self._tree = tree  # the lookup reads the tree's tables
+        self.level = level
+        self._h = lib().oref_lookup_open(tree._h, level)
+        if not self._h:
+            raise OracleError(ERR_LEVEL, "oref_lookup_open")
+
+    def range(self, kind: int, r0: int, r1: int):
+        """(offsets relative to box r0, entries) of receiver boxes [r0, r1)."""
+        off = np.empty(r1 - r0 + 1, dtype=np.uint32)
+        ent = np.empty((r1 - r0) * (27 if kind == 2 else 189), dtype=np.uint32)
+        st = lib().oref_list_range(self._h, kind, r0, r1, _ptr(off), _ptr(ent))
+        if st != OK:
+            raise OracleError(st, "oref_list_range")
+        return off, ent[:int(off[-1])]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().oref_lookup_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

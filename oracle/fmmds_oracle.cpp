@@ -427,6 +427,43 @@ int oref_box_list(const oref_tree* t, int kind, uint32_t level, uint32_t recv_bo
   return (int)tmp.size();
 }
 
+// A level's source-box membership table, kept for repeated range queries.
+struct oref_lookup {
+  const oref_tree* t;
+  uint32_t level;
+  Lookup look;
+  oref_lookup(const oref_tree* tree, uint32_t l)
+      : t(tree), level(l), look(tree->set(0).lv[l], l, true) {}
+};
+
+oref_lookup* oref_lookup_open(const oref_tree* t, uint32_t level) {
+  if (!t || level < 2 || level > t->depth) return nullptr;
+  try {
+    return new oref_lookup(t, level);
+  } catch (const std::bad_alloc&) {
+    return nullptr;
+  }
+}
+
+void oref_lookup_close(oref_lookup* lk) { delete lk; }
+
+int oref_list_range(const oref_lookup* lk, int kind, uint32_t r0, uint32_t r1,
+                    uint32_t* offsets, uint32_t* entries) {
+  if (!lk || !offsets || !entries || (kind != 2 && kind != 4)) return OREF_ERR_ARG;
+  const Level& rl = lk->t->set(1).lv[lk->level];
+  if (r0 > r1 || r1 > rl.key.size()) return OREF_ERR_ARG;
+  std::vector<uint32_t> tmp;
+  uint32_t total = 0;
+  for (uint32_t j = r0; j < r1; ++j) {
+    offsets[j - r0] = total;
+    box_list(lk->look, kind, rl.key[j], lk->level, tmp);
+    std::copy(tmp.begin(), tmp.end(), entries + total);
+    total += (uint32_t)tmp.size();
+  }
+  offsets[r1 - r0] = total;
+  return OREF_OK;
+}
+
 
 // ---------------------------------------------------------------------------
 // Simulated partition and source box types (Section 3).

@@ -70,6 +70,21 @@ int oref_list(const oref_tree* t, int kind, uint32_t level, uint32_t* offsets, u
 int oref_box_list(const oref_tree* t, int kind, uint32_t level, uint32_t recv_box,
                   uint32_t* entries);
 
+/* Lists of the receiver boxes [r0, r1) of one level, from the same
+ * definition, without building every list of the tree (complete checks of
+ * large builds, a range at a time). A lookup holds the level's source-box
+ * membership table; it reads the tree, which must outlive it, and any number
+ * of threads may query one lookup at once.
+ *   offsets: r1 - r0 + 1 values, relative to box r0 (offsets[0] = 0);
+ *   entries: room for 27 (E2) or 189 (E4) entries per box.
+ * oref_lookup_open returns NULL for a level outside [2, depth] or when out of
+ * memory. */
+typedef struct oref_lookup oref_lookup;
+oref_lookup* oref_lookup_open(const oref_tree* t, uint32_t level);
+void oref_lookup_close(oref_lookup* lk);
+int oref_list_range(const oref_lookup* lk, int kind, uint32_t r0, uint32_t r1,
+                    uint32_t* offsets, uint32_t* entries);
+
 /* Simulated partition (Section 3.2): the rank owning every Morton index of
  * level l_par (dense, 8^l_par entries), consecutive Morton ranges balanced
  * by receiver points. Needs 3 <= l_par <= depth. */

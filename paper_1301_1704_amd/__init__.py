@@ -105,6 +105,10 @@ def _lib():
         L.fmmds_batch_sort_items.restype = _u32
         L.fmmds_batch_free.argtypes = [_vp]
         L.fmmds_batch_free.restype = None
+        L.fmmds_build_batch.argtypes = [_vp, _vp, _vp, _u32, C.POINTER(Options), C.POINTER(_vp)]
+        L.fmmds_build_batch.restype = C.c_int
+        L.fmmds_free_batch.argtypes = [_vp]
+        L.fmmds_free_batch.restype = None
         L.fmmds_partition.argtypes = [C.POINTER(TreeStruct), _u32, _u32, _vp, _vp]
         L.fmmds_partition.restype = C.c_int
         L.fmmds_box_types.argtypes = [C.POINTER(TreeStruct), _u32, _vp, _u32, _vp, _vp]
@@ -136,7 +140,8 @@ def exported_symbols():
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
             "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types",
-            "fmmds_near_field", "fmmds_rebuild", "fmmds_build_dense"]
+            "fmmds_near_field", "fmmds_rebuild", "fmmds_build_dense", "fmmds_build_batch",
+            "fmmds_free_batch"]
 
 
 class DisplaceSet(C.Structure):
@@ -480,7 +485,8 @@ class Batch:
     """Batched build of many point sets (fmmds_batch_*): plan once, launch
     many times (optionally as a replayed HIP graph), read per-set trees."""
 
-    def __init__(self, set_offsets, levels, *, stream=None, allocator: str = "pool"):
+    def __init__(self, set_offsets, levels, *, stream=None, allocator: str = "pool",
+                 build_from=None):
         import torch
         L = _lib()
         self._off = np.ascontiguousarray(set_offsets, dtype=np.uint64)
@@ -498,10 +504,20 @@ class Batch:
             self._keep = _TORCH_ALLOC
             opt.alloc, opt.release = self._keep.alloc, self._keep.release
         h = _vp()
-        st = L.fmmds_batch_create(self._off.ctypes.data_as(_vp), self._lev.ctypes.data_as(_vp),
-                                  self.n_sets, C.byref(opt), C.byref(h))
+        if build_from is None:
+            st = L.fmmds_batch_create(self._off.ctypes.data_as(_vp),
+                                      self._lev.ctypes.data_as(_vp), self.n_sets, C.byref(opt),
+                                      C.byref(h))
+            what = "fmmds_batch_create"
+        else:
+            if self._stream is None:
+                torch.cuda.current_stream().synchronize()
+            st = L.fmmds_build_batch(build_from.data_ptr(), self._off.ctypes.data_as(_vp),
+                                     self._lev.ctypes.data_as(_vp), self.n_sets, C.byref(opt),
+                                     C.byref(h))
+            what = "fmmds_build_batch"
         if st != OK:
-            raise FmmdsError(st, "fmmds_batch_create")
+            raise FmmdsError(st, what)
         self._h = h
         self._torch = torch
 
@@ -536,7 +552,7 @@ class Batch:
 
     def free(self):
         if getattr(self, "_h", None) is not None:
-            _lib().fmmds_batch_free(self._h)
+            _lib().fmmds_free_batch(self._h)
             self._h = None
 
     def __del__(self):
@@ -544,3 +560,10 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+def build_batch(xyz, set_offsets, levels, *, stream=None, allocator: str = "pool") -> Batch:
+    """The batched form in one call (fmmds_build_batch): every set of the
+    concatenated coordinates `xyz` (float32 CUDA tensor (total, 3)) built and
+    waited for; per-set trees from .tree(i)."""
+    return Batch(set_offsets, levels, stream=stream, allocator=allocator, build_from=xyz)

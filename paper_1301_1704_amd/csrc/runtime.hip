@@ -472,6 +472,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
   P.on = g_prof_on.load() != 0;
   P.only = g_prof_only.load();
   P.s = st;
+  hipStream_t side = nullptr;  // the receivers' stream, once this build has used it
   try {
     SetBufs sets[2];
     sets[0].xyz = src_xyz;
@@ -663,6 +664,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     hipStream_t st1 = st;
     if (two) {
       st1 = side_stream();
+      side = st1;
       EventRef e0 = record_event(st);
       if (e0->ev) ck(hipStreamWaitEvent(st1, e0->ev, 0));
     }
@@ -1039,8 +1041,12 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     result = FMMDS_ERR_NOMEM;
   }
   if (result != FMMDS_OK) {
+    // Work of this build may still use the buffers: wait for the caller's
+    // stream and, when the receivers' chain was enqueued, the side stream
+    // (not the whole device).
     (void)hipGetLastError();
-    (void)hipDeviceSynchronize();  // a second stream may still use the buffers
+    if (side) (void)hipStreamSynchronize(side);
+    (void)hipStreamSynchronize(st);
     (void)hipGetLastError();
     P.drop();
     temps.release_all();
@@ -1806,6 +1812,27 @@ uint32_t fmmds_batch_sort_items(const fmmds_batch* b) {
 }
 
 void fmmds_batch_free(fmmds_batch* b) { fmmds::batch_free((fmmds::BatchImpl*)b); }
+
+fmmds_status fmmds_build_batch(const float* xyz, const uint64_t* set_offsets,
+                               const uint8_t* levels, uint32_t n_sets, const fmmds_options* opt,
+                               fmmds_batch** out) {
+  if (!out) return FMMDS_ERR_ARG;
+  *out = nullptr;
+  if (!xyz) return FMMDS_ERR_ARG;
+  fmmds_batch* b = nullptr;
+  fmmds_status st = fmmds::batch_create(set_offsets, levels, n_sets, opt, &b);
+  if (st != FMMDS_OK) return st;
+  st = fmmds::batch_launch((fmmds::BatchImpl*)b, xyz, 0);
+  if (st == FMMDS_OK) st = fmmds::batch_wait((fmmds::BatchImpl*)b);
+  if (st != FMMDS_OK) {
+    fmmds::batch_free((fmmds::BatchImpl*)b);
+    return st;
+  }
+  *out = b;
+  return FMMDS_OK;
+}
+
+void fmmds_free_batch(fmmds_batch* b) { fmmds::batch_free((fmmds::BatchImpl*)b); }
 
 fmmds_status fmmds_displace(const fmmds_displace_set* sets, uint32_t n_sets, float sigma,
                             float* out, void* stream) {

@@ -53,6 +53,29 @@ def test_batch_sets_match_oracle(F, oracle_lib, seed, n_sets):
     torch.cuda.synchronize()
 
 
+def test_build_batch_one_call(F, oracle_lib):
+    """fmmds_build_batch (create, launch, wait in one call) gives every set
+    the oracle's build, and the returned batch launches again like any other."""
+    import torch
+    xyz, off, lev = _small_batch(21, 9)
+    x = parity.to_gpu(xyz)
+    b = F.build_batch(x, off, lev)
+    for i in range(9):
+        pts = xyz[int(off[i]):int(off[i + 1])]
+        o = oracle_lib.OracleTree(pts, None, key_bits=64, max_level=int(lev[i]))
+        _compare_set(b.tree(i), o)
+    first = b.tree(3).host_list(4, int(lev[3]))
+    b.launch(x)
+    b.wait()
+    again = b.tree(3).host_list(4, int(lev[3]))
+    assert all(np.array_equal(u, v) for u, v in zip(first, again))
+    b.free()
+    with pytest.raises(F.FmmdsError) as e:
+        F.build_batch(x, off, np.full(9, 30, np.uint8))
+    assert e.value.status == F.ERR_ARG
+    torch.cuda.synchronize()
+
+
 def test_batch_mixed_levels_and_tiny_sets(F, oracle_lib):
     """Sets of 1, 2 and a few points, and levels 2..7 in one batch."""
     parts = [I.uniform_points(5, 1), I.uniform_points(6, 2), I.uniform_points(7, 9),

@@ -1,10 +1,10 @@
 """GPU parity: libfmmds through its C ABI against the CPU oracle.
 
 Bit-exact on every output (all integer tables and lists, FP32 coordinates
-copied bit for bit). Small cases compare every array; the full-size
-workloads (two 2^24-point sets) compare every table array and sampled
-receiver lists against the oracle's per-box definition, plus structure
-properties of the whole lists.
+copied bit for bit). Every case compares every array: the full-size
+workloads (two 2^24-point sets) compare the lists a range of receiver
+boxes at a time against the oracle's lists of the same boxes, computed from
+the definition on several host threads.
 """
 import os
 import sys
@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 def _say(msg):
     print(msg, flush=True)
-    sys.stdout.flush()
+    print(msg, file=sys.__stderr__, flush=True)  # past pytest's capture: long cases show progress
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +49,7 @@ def _run(F, oracle_lib, src, recv, *, L, kb=64, s=0, lists="full", allocator="po
     if lists == "full":
         parity.compare_lists(g, o)
     else:
-        parity.compare_lists_sampled(g, o)
+        parity.compare_lists_chunked(g, o)
     return g, o
 
 
@@ -196,19 +196,29 @@ def test_list_level_errors(F):
 
 # --------------------------------------------------------------- full size
 
+@pytest.mark.timeout(600)
+def test_mid_uniform_2x2p21_L7_whole_csr(F, oracle_lib):
+    """Two 2^21-point uniform sets at max level 7 (every level-7 box holds
+    about one point): thousands of tiles per look-back chain and list-fill
+    grid, compared against the oracle's whole lists."""
+    src, recv = I.uniform_points(12, 1 << 21), I.uniform_points(13, 1 << 21)
+    _run(F, oracle_lib, src, recv, L=7)[0].free()
+
+
 @pytest.mark.timeout(900)
 def test_full_uniform_2x2p24_L8(F, oracle_lib):
     """Two independent 2^24-point uniform sets, max level 8, 64-bit keys: the
-    configuration the benchmark times."""
+    configuration the benchmark times. Every table, offset and list entry."""
     c = I.config_plain_uniform()
-    _run(F, oracle_lib, c["src"], c["recv"], L=8, lists="sampled")[0].free()
+    _run(F, oracle_lib, c["src"], c["recv"], L=8, lists="chunked")[0].free()
 
 
 @pytest.mark.timeout(900)
 def test_full_nonuniform_2x2p24_L10_s64(F, oracle_lib):
-    """Two 2^24-point sphere + cluster sets, max level 10, cluster size 64."""
+    """Two 2^24-point sphere + cluster sets, max level 10, cluster size 64.
+    Every table, offset and list entry."""
     c = I.config_plain_nonuniform()
-    g, o = _run(F, oracle_lib, c["src"], c["recv"], L=10, s=64, lists="sampled")
+    g, o = _run(F, oracle_lib, c["src"], c["recv"], L=10, s=64, lists="chunked")
     assert g.depth == o.depth
     g.free()
 

@@ -1,7 +1,8 @@
 """The serving loop: every request's tables and lists in the continuous-
-batching mix equal a plain build of the same displaced coordinates alone
-(tolerance 0: all outputs are integers or bit copies); memory admission
-waits instead of overcommitting and rejects a request that can never fit."""
+batching mix equal the CPU oracle's build of the same displaced coordinates
+and a plain GPU build of them alone (tolerance 0: all outputs are integers or
+bit copies); memory admission waits instead of overcommitting and rejects a
+request that can never fit."""
 import os
 
 import numpy as np
@@ -37,11 +38,24 @@ def _digest(t):
     return out
 
 
+def _oracle_digest(o):
+    """The same arrays as _digest, from the oracle (shared set, 64-bit keys)."""
+    out = [o.perm(0)]
+    for l in range(o.depth + 1):
+        out += [o.keys(0, l), o.begin(0, l)]
+        if l >= 1:
+            out.append(o.parent(0, l))
+    for l in range(2, o.depth + 1):
+        for k in (2, 4):
+            out += list(o.list(k, l))
+    return out
+
+
 def _systems(n=10, seed=3):
     return I.serving_systems(n, seed, 10, 16)
 
 
-def test_mix_equals_alone(F):
+def test_mix_equals_alone(F, oracle_lib):
     import torch
     from paper_1301_1704_amd import serving as S
     systems, levels = _systems()
@@ -67,6 +81,13 @@ def test_mix_equals_alone(F):
         assert len(alone) == len(got[rid])
         for a, b in zip(alone, got[rid]):
             assert np.array_equal(a, b), rid
+        o = oracle_lib.OracleTree(x.cpu().numpy(), None, key_bits=64,
+                                  max_level=int(levels[r.system]), with_lists=True)
+        ref = _oracle_digest(o)
+        o.close()
+        assert len(ref) == len(got[rid])
+        for i, (a, b) in enumerate(zip(ref, got[rid])):
+            assert a.dtype == b.dtype and np.array_equal(a, b), (rid, i)
     # several requests shared a batch (continuous batching actually batched)
     launched = {}
     for r in reqs:

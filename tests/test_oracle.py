@@ -508,3 +508,81 @@ def test_dense_histogram_scans_give_the_tables(oracle_lib):
                                   prev_rank[nonempty >> 3])
         prev_rank = scanned_rank
     o.close()
+
+
+def test_list_ranges_equal_whole_lists(oracle_lib):
+    """The range queries that check full-size builds return, for any range of
+    receiver boxes, exactly the slice of the whole lists (both built from the
+    definition of Section 1.4), also under concurrent queries."""
+    import concurrent.futures as cf
+    from paper_1301_1704_amd import inputs as I
+    src = I.sphere_cluster_points(601, 602, 20000)
+    recv = I.uniform_points(603, 15000)
+    o = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=6, with_lists=True)
+    for l in range(2, 7):
+        lk = o.lookup(l)
+        for kind in (2, 4):
+            off, ent = o.list(kind, l)
+            n = off.size - 1
+            cuts = sorted({0, 1, n // 7, n // 3, n // 2, n - 1, n})
+            ranges = [(a, b) for a, b in zip(cuts[:-1], cuts[1:])] + [(0, n), (n, n)]
+            with cf.ThreadPoolExecutor(4) as ex:
+                got = list(ex.map(lambda r: lk.range(kind, *r), ranges))
+            for (a, b), (ro, re) in zip(ranges, got):
+                assert np.array_equal(ro, off[a:b + 1] - off[a])
+                assert np.array_equal(re, ent[off[a]:off[b]])
+        lk.close()
+    with pytest.raises(oracle_lib.OracleError):
+        o.lookup(7)
+    o.close()
+
+
+class _HostTree:
+    """A stand-in for a GPU tree holding given host lists (for the checker's
+    own test on the CPU)."""
+
+    def __init__(self, o, lists):
+        self.depth = o.depth
+        self._o = o
+        self._lists = lists
+
+    def n_boxes(self, s, l):
+        return self._o.n_boxes(s, l)
+
+    def host_list(self, kind, l):
+        off, ent = self._lists[(kind, l)]
+        return off.copy(), ent.copy()
+
+
+def test_chunked_list_check_finds_a_planted_difference(oracle_lib):
+    """The complete full-size list check accepts the oracle's own lists and
+    rejects one changed entry, one changed offset and one dropped entry."""
+    import parity
+    from paper_1301_1704_amd import inputs as I
+    src, recv = I.uniform_points(611, 30000), I.uniform_points(612, 25000)
+    o = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=6, with_lists=True)
+    lists = {(k, l): o.list(k, l) for l in range(2, 7) for k in (2, 4)}
+    plain = oracle_lib.OracleTree(src, recv, key_bits=64, max_level=6, with_lists=False)
+    parity.compare_lists_chunked(_HostTree(o, lists), plain, chunk=1000, threads=3)
+
+    def planted(change):
+        bad = {k: (v[0].copy(), v[1].copy()) for k, v in lists.items()}
+        change(bad)
+        with pytest.raises(AssertionError):
+            parity.compare_lists_chunked(_HostTree(o, bad), plain, chunk=1000, threads=3)
+
+    def entry(b):
+        b[(4, 6)][1][12345] ^= 1
+
+    def offset(b):
+        b[(2, 5)][0][777] += 1
+
+    def dropped(b):
+        off, ent = b[(4, 4)]
+        b[(4, 4)] = (np.concatenate([off[:10], off[10:] - 1]).astype(np.uint32),
+                     np.delete(ent, int(off[9])))
+
+    for change in (entry, offset, dropped):
+        planted(change)
+    o.close()
+    plain.close()
