@@ -517,8 +517,9 @@ def bench_dense(F, torch, src, recv, kw, reps=5):
 
 def bench_serving(F, torch, args):
     """Continuous-batching serving of rebuild requests from 64 moving particle
-    systems (2^14..2^22 points, 64 Gaussian clusters), Poisson arrivals at 0.7x
-    the saturated one-at-a-time build rate of the same mix, against the
+    systems (2^14..2^22 points, 64 Gaussian clusters): Poisson arrivals at
+    0.3, 0.5, 0.7 and 0.9x the saturated one-at-a-time build rate of the same
+    mix, and every request at once (saturation), each against the
     one-at-a-time loop replaying the identical arrival trace."""
     from paper_1301_1704_amd import inputs as I
     from paper_1301_1704_amd import serving as S
@@ -534,30 +535,70 @@ def bench_serving(F, torch, args):
     torch.cuda.synchronize()
     sat = len(xs) / (time.perf_counter() - t0)
     del xs
-    rate = 0.7 * sat
     n_req = args.serving_warmup + args.serving_requests
-    arr, pick = I.poisson_trace(n_req, rate, len(systems))
     srv = S.Server(systems, levels, n_slots=4)
-    reqs = srv.run(arr, pick)
-    evict = srv.evictions
+    # plans and graphs of the mix made once, outside every measurement
+    warm_arr, warm_pick = I.poisson_trace(4 * len(systems), 0.7 * sat, len(systems), seed=81)
+    srv.run(warm_arr, warm_pick)
+    sweep = []
+    for frac in (0.3, 0.5, 0.7, 0.9, None):
+        rate = float("inf") if frac is None else frac * sat
+        arr, pick = I.poisson_trace(n_req, sat if frac is None else rate, len(systems))
+        if frac is None:
+            arr = np.zeros_like(arr)  # every request waiting at once
+        srv.reset(keep_plans=True)
+        reused0 = srv.reused
+        reqs = srv.run(arr, pick)
+        ours = S.latency_stats(reqs, skip=args.serving_warmup)
+        batch_sizes = {}
+        for r in reqs[args.serving_warmup:]:
+            batch_sizes[r.launched] = batch_sizes.get(r.launched, 0) + 1
+        seq = S.latency_stats(S.run_sequential(systems, levels, arr, pick),
+                              skip=args.serving_warmup)
+        point = {"load": "saturated" if frac is None else frac,
+                 "arrival_rate_per_s": None if frac is None else rate, **ours,
+                 "mean_requests_per_batch": float(np.mean(list(batch_sizes.values()))),
+                 "plans_reused": srv.reused - reused0, "plans": len(srv.entries),
+                 "evictions": srv.evictions, "plain_sequential": seq,
+                 "p99_vs_plain": seq["p99_ms"] / ours["p99_ms"] if ours["p99_ms"] > 0 else None,
+                 "builds_per_s_vs_plain": ours["builds_per_s"] / seq["builds_per_s"]}
+        sweep.append(point)
+        log(f"serving {point['load']}: p50 {ours['p50_ms']:.2f} ms p99 {ours['p99_ms']:.2f} ms "
+            f"{ours['builds_per_s']:.0f} builds/s ({point['mean_requests_per_batch']:.2f} per "
+            f"batch); one-at-a-time p50 {seq['p50_ms']:.2f} ms p99 {seq['p99_ms']:.2f} ms "
+            f"{seq['builds_per_s']:.0f} builds/s")
     srv.close()
-    ours = S.latency_stats(reqs, skip=args.serving_warmup)
-    batch_sizes = {}
-    for r in reqs[args.serving_warmup:]:
-        batch_sizes[r.launched] = batch_sizes.get(r.launched, 0) + 1
-    seq = S.latency_stats(S.run_sequential(systems, levels, arr, pick), skip=args.serving_warmup)
-    res = {"workload": "64 systems, 2^14..2^22 points (log-uniform), 64-cluster Gaussian, "
-                       "levels 3..6, N(0, 1e-3) displacement per step",
-           "arrival_rate_per_s": rate, "saturated_plain_rate_per_s": sat,
-           "warmup_requests": args.serving_warmup, **ours, "slots": 4,
-           "mean_requests_per_batch": float(np.mean(list(batch_sizes.values()))),
-           "evictions": evict,
-           "plain_sequential": seq,
-           "p99_vs_plain": seq["p99_ms"] / ours["p99_ms"] if ours["p99_ms"] > 0 else None}
-    log(f"serving: p50 {ours['p50_ms']:.2f} ms p99 {ours['p99_ms']:.2f} ms "
-        f"{ours['builds_per_s']:.0f} builds/s; one-at-a-time p50 {seq['p50_ms']:.2f} ms "
-        f"p99 {seq['p99_ms']:.2f} ms {seq['builds_per_s']:.0f} builds/s")
-    return res
+    head = next(p for p in sweep if p["load"] == 0.7)
+    return {"workload": "64 systems, 2^14..2^22 points (log-uniform), 64-cluster Gaussian, "
+                        "levels 3..6, N(0, 1e-3) displacement per step",
+            "saturated_plain_rate_per_s": sat, "warmup_requests": args.serving_warmup,
+            "slots": 4, **{k: v for k, v in head.items() if k != "load"}, "sweep": sweep}
+
+
+PASSES = ("keygen", "sort_pass", "leaf", "level", "scan_counts")
+
+
+def roofline_passes(breakdown: dict, workload_name: str) -> dict:
+    """The sort and compaction passes against the HBM peak: per kernel class,
+    algorithmic bytes of all its launches over their summed event-measured
+    durations (each kernel timed alone), and the counter traffic per launch
+    when the committed counter summary matches the kernel's source."""
+    out = {}
+    for k in PASSES:
+        b = breakdown.get(k)
+        if not b or b["total_ms"] <= 0:
+            continue
+        achieved = b["bytes"] / (b["total_ms"] * 1e6)
+        per_launch = b["bytes"] / b["launches"]
+        tr = counter_traffic(workload_name, k)
+        out[k] = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(achieved / HBM_PEAK_GBS, 4), "launches": b["launches"],
+                  "avg_launch_us": round(1e3 * b["total_ms"] / b["launches"], 2),
+                  "bytes_per_launch": round(per_launch),
+                  "traffic": None if tr is None else tr["read"] + tr["write"],
+                  "traffic_over_algorithmic":
+                      None if tr is None else round((tr["read"] + tr["write"]) / per_launch, 3)}
+    return out
 
 
 def main():
@@ -656,9 +697,11 @@ def main():
     profile = not args.no_profile
     breakdown, dominant = {}, None
     if profile:
-        # Untimed calibration: every kernel timed, to find the dominant one.
+        # Untimed calibration: every kernel timed, alone (the receivers' chain
+        # on the build stream too), to find the dominant kernel and the
+        # sort / compaction passes' own rates.
         F.profile_reset()
-        F.profile_enable(True)
+        F.profile_enable(True, serial=True)
         for _ in range(2):
             F.build(src, recv, **kw).free()
         torch.cuda.synchronize()
@@ -711,6 +754,7 @@ def main():
                 "read_bytes": tr["read"], "write_bytes": tr["write"],
                 "over_algorithmic": (tr["read"] + tr["write"]) / per_launch,
                 "counters": "profiles/" + tr["source"]}
+        line["roofline_passes"] = roofline_passes(breakdown, args.workload)
         line["kernels"] = {k: {"launches": b["launches"],
                                "avg_us": round(1e3 * b["total_ms"] / b["launches"], 2),
                                "GBps": round(b["bytes"] / (b["total_ms"] * 1e6), 1)}

@@ -378,7 +378,10 @@ typedef struct fmmds_kernel_stat {
 
 /* on != 0 enables timing; `only` = NULL times every kernel, else only the
  * kernel of that name (so a timed run carries two events per launch of one
- * kernel instead of two per launch of every kernel). */
+ * kernel instead of two per launch of every kernel). on == 2 also runs the
+ * receivers' chain of fmmds_build on the build stream instead of the
+ * library's second stream, so that no two kernels of a build overlap and
+ * each measured duration is that kernel's alone (the results are the same). */
 void fmmds_profile_enable(int on, const char* only);
 void fmmds_profile_reset(void);
 /* Copies up to `cap` entries into `out` (host); returns the number of kernels

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmmds.so")
 MAX_LEVEL = 21
 
-OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_LEVEL, ERR_OVERFLOW = 0, 1, 2, 3, 4, 5, 6
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_LEVEL, ERR_OVERFLOW = range(7)
 SRC, RECV = 0, 1
 
 _u32, _u64, _vp = C.c_uint32, C.c_uint64, C.c_void_p
@@ -192,10 +192,12 @@ def trim():
     _lib().fmmds_trim()
 
 
-def profile_enable(on: bool = True, only: str | None = None):
+def profile_enable(on: bool = True, only: str | None = None, serial: bool = False):
     """Time kernels of later builds with HIP events on the build stream: every
-    kernel, or only the one named `only`."""
-    _lib().fmmds_profile_enable(1 if on else 0, None if only is None else only.encode())
+    kernel, or only the one named `only`. `serial`: the receivers' chain runs
+    on the build stream too, so that each kernel is timed alone."""
+    mode = (2 if serial else 1) if on else 0
+    _lib().fmmds_profile_enable(mode, None if only is None else only.encode())
 
 
 def profile_reset():
@@ -332,12 +334,18 @@ class Tree:
         return out, sizes
 
     # -- near-field sum over E2 (Algorithm 2 with a Laplace kernel)
-    def near_field(self, charges=None, count_pairs: bool = False, stream=None):
+    def near_field(self, charges=None, count_pairs: bool = False, stream=None, phi=None):
         """phi per receiver point (original order) as a float32 CUDA tensor,
-        and the number of pairs visited (if count_pairs, else None)."""
+        and the number of pairs visited (if count_pairs, else None). `phi`:
+        an output tensor to fill (float32, n_recv values) instead of a new
+        one."""
         import torch
         s = stream if stream is not None else torch.cuda.current_stream()
-        phi = torch.empty(self.n_recv, dtype=torch.float32, device="cuda")
+        if phi is None:
+            phi = torch.empty(self.n_recv, dtype=torch.float32, device="cuda")
+        elif phi.dtype != torch.float32 or not phi.is_cuda or phi.numel() != self.n_recv or \
+                not phi.is_contiguous():
+            raise ValueError("phi: contiguous float32 CUDA tensor of n_recv values")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda") if count_pairs else None
         if charges is not None:
             if charges.dtype != torch.float32 or not charges.is_cuda or \

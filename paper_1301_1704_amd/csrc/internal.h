@@ -221,11 +221,16 @@ void launch_types_crit(bool key64, const BoxTypeLevel& a, hipStream_t s);
 void launch_types_deep(bool key64, const BoxTypeLevel& a, hipStream_t s);
 
 // ---- nearfield.hip
+// Receiver boxes of more than kNearDenseMin points go to the dense path.
+constexpr uint32_t kNearDenseMin = 8;
+constexpr uint32_t kNearCounters = 2;
+uint64_t near_field_max_tasks(uint32_t n_recv);  // dense-path tasks for n_recv receivers
 void launch_pack_sources(const float* sxyz, const uint32_t* sperm, const float* charges,
-                         uint32_t n, float4* out, hipStream_t s);
-void launch_near_field(uint32_t n_rbox, const uint32_t* rbegin, const float* rxyz,
-                       const uint32_t* rperm, const uint32_t* e2_off, const uint32_t* e2_ent,
-                       const uint32_t* sbegin, const float4* src, float* phi,
-                       unsigned long long* n_pairs, hipStream_t s);
+                         uint32_t n, float4* out, uint32_t* counters, hipStream_t s);
+void launch_near_field(uint32_t n_rbox, uint32_t n_recv, const uint32_t* rbegin,
+                       const float* rxyz, const uint32_t* rperm, const uint32_t* e2_off,
+                       const uint32_t* e2_ent, const uint32_t* sbegin, const float4* src,
+                       float* phi, unsigned long long* n_pairs, uint2* tasks,
+                       uint32_t* counters, hipStream_t s);
 
 }  // namespace fmmds

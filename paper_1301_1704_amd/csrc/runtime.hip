@@ -662,7 +662,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       Dn.rank = temps.get<uint32_t>(sets[s].n);
     }
     hipStream_t st1 = st;
-    if (two) {
+    // (profiling with on == 2 keeps both chains on the build stream, so that
+    // every kernel's event-measured duration is its own)
+    if (two && g_prof_on.load() != 2) {
       st1 = side_stream();
       side = st1;
       EventRef e0 = record_event(st);
@@ -1707,18 +1709,37 @@ fmmds_status box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t* owne
   return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
 }
 
+// Bytes of the near-field scratch: packed sources, the dense path's tasks,
+// its counters.
+struct NearScratch {
+  size_t src_b, task_b, total;
+  explicit NearScratch(const fmmds_tree* t)
+      : src_b(round_up((size_t)t->n_src * 16, 256)),
+        task_b(round_up(near_field_max_tasks(t->n_recv) * sizeof(uint2), 256)),
+        total(src_b + task_b + 256) {}
+};
+
+void near_field_launch(const fmmds_tree* t, const NearScratch& ns, char* scratch,
+                       const float* charges, float* phi, uint64_t* n_pairs, hipStream_t st) {
+  const TreeImpl* impl = (const TreeImpl*)t->impl;
+  const uint32_t D = t->depth;
+  float4* src4 = (float4*)scratch;
+  uint2* tasks = (uint2*)(scratch + ns.src_b);
+  uint32_t* counters = (uint32_t*)(scratch + ns.src_b + ns.task_b);
+  launch_pack_sources(t->src_sorted_xyz, t->src_perm, charges, t->n_src, src4, counters, st);
+  launch_near_field(t->recv[D].n, t->n_recv, t->recv[D].begin, t->recv_sorted_xyz, t->recv_perm,
+                    impl->lists[D].off[0], impl->lists[D].ent[0], t->src[D].begin, src4, phi,
+                    (unsigned long long*)n_pairs, tasks, counters, st);
+}
+
 fmmds_status near_field(const fmmds_tree* t, const float* charges, float* phi,
                         uint64_t* n_pairs, hipStream_t st) {
   if (!t || !t->impl || !phi) return FMMDS_ERR_ARG;
-  const TreeImpl* impl = (const TreeImpl*)t->impl;
-  const uint32_t D = t->depth;
-  void* src4 = cache_alloc((size_t)t->n_src * 16, st);
-  if (!src4) return FMMDS_ERR_NOMEM;
-  launch_pack_sources(t->src_sorted_xyz, t->src_perm, charges, t->n_src, (float4*)src4, st);
-  launch_near_field(t->recv[D].n, t->recv[D].begin, t->recv_sorted_xyz, t->recv_perm,
-                    impl->lists[D].off[0], impl->lists[D].ent[0], t->src[D].begin,
-                    (const float4*)src4, phi, (unsigned long long*)n_pairs, st);
-  cache_release(src4, st);
+  const NearScratch ns(t);
+  char* scratch = (char*)cache_alloc(ns.total, st);
+  if (!scratch) return FMMDS_ERR_NOMEM;
+  near_field_launch(t, ns, scratch, charges, phi, n_pairs, st);
+  cache_release(scratch, st);
   return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
 }
 
@@ -1906,7 +1927,7 @@ void fmmds_profile_enable(int on, const char* only) {
       if (std::strcmp(only, fmmds::kClassName[k]) == 0) cls = k;
   }
   fmmds::g_prof_only.store(cls);
-  fmmds::g_prof_on.store(on ? 1 : 0);
+  fmmds::g_prof_on.store(on == 2 ? 2 : on ? 1 : 0);
 }
 
 void fmmds_profile_reset(void) {

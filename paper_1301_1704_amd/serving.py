@@ -14,14 +14,19 @@ on one GPU:
   the waiting requests (at most one per system, since a system's steps are
   sequential) are packed into one batched build (fmmds_batch_*) and launched
   on that stream, so work from different ticks overlaps on the device;
-- a batch is admitted only if its device footprint (fmmds_batch_footprint)
-  fits the HBM budget next to everything still resident; if nothing is in
-  flight and even one request does not fit, the oldest resident tables are
-  evicted (their systems are rebuilt from scratch on their next request);
-  a request that does not fit an empty budget fails with ERR_NOMEM;
+- a batch of the same systems on the same slot is planned once and kept: its
+  input buffer and its HIP graph (captured at the first launch) are reused by
+  every later batch of those systems there, so a repeated batch costs one
+  displacement and one graph launch on the host;
+- a new plan is admitted only if its device footprint (fmmds_batch_footprint
+  plus its input buffer) fits the HBM budget next to everything resident;
+  planned batches are freed least recently used first, first those that hold
+  no system's current tables, then (with nothing in flight) any idle one
+  (their systems are rebuilt from scratch on their next request); a request
+  that does not fit an empty budget fails with ERR_NOMEM;
 - each system keeps its latest tables resident on the GPU (a view into the
-  batch that built them); a batch is released once none of its systems still
-  points at it.
+  batch that built them) until its next request reuses that batch or the
+  batch is freed.
 
 All compute is the library's; this is host scheduling only. The sequential
 baseline replays the same arrival trace with one fmmds_build per request on
@@ -30,7 +35,7 @@ one stream.
 from __future__ import annotations
 
 import time
-from collections import deque
+from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -51,26 +56,33 @@ class Request:
 
 
 @dataclass
-class _Live:
+class _Entry:
+    """A planned batch for one (slot, system tuple), kept for reuse: its
+    input buffer and, after the first launch, its captured graph are replayed
+    by later batches of the same systems on the same slot."""
+    key: tuple
+    slot: int
     batch: object
-    refs: int
+    xbuf: object
     nbytes: int
+    refs: int = 0          # systems whose resident tables are this batch's
+    in_flight: bool = False
+    launches: int = 0
 
 
 @dataclass
 class _Slot:
     stream: object
-    batch: object = None
+    entry: object = None
     event: object = None
     reqs: list = field(default_factory=list)
-    xbuf: object = None
 
 
 class Server:
     def __init__(self, systems, levels, *, n_slots: int = 4, hbm_budget: int | None = None,
                  max_batch_points: int = 1 << 24, max_batch_sets: int = 64,
                  sigma: float = 1e-3, seed: int = 8, keep_inputs=(),
-                 stall_seconds: float = 60.0):
+                 stall_seconds: float = 60.0, graphs: bool = True):
         import torch
         import paper_1301_1704_amd as F
         self.torch, self.F = torch, F
@@ -86,6 +98,7 @@ class Server:
         self.budget = hbm_budget
         self.keep_inputs = set(keep_inputs)  # request ids whose inputs are kept (tests)
         self.stall_seconds = stall_seconds
+        self.graphs = graphs
         self._prewarm()
         self.reset()
 
@@ -100,25 +113,35 @@ class Server:
                 F.displace([(x, 1, 0)], 0.0, stream=slot.stream)
             b = F.Batch(np.asarray([0, 100, 300], np.uint64), np.asarray([2, 3], np.uint8),
                         stream=slot.stream)
-            b.launch(x)
+            b.launch(x, capture=self.graphs)
             b.wait()
             b.free()
         torch.cuda.synchronize()
 
     # ------------------------------------------------------------- state
-    def reset(self):
+    def reset(self, keep_plans: bool = False):
+        """Systems back to their initial points; with keep_plans the planned
+        batches (and their graphs) stay for reuse, holding no tables."""
         torch = self.torch
         torch.cuda.synchronize()
+        entries = getattr(self, "entries", None) or OrderedDict()
+        if keep_plans:
+            for e in entries.values():
+                e.refs, e.in_flight = 0, False
+        else:
+            for e in entries.values():
+                e.batch.free()
+            entries = OrderedDict()
         self.x = [torch.from_numpy(p).cuda() for p in self.x0]
         self.step = [0] * len(self.x0)
-        self.latest = [None] * len(self.x0)     # (live id, set index) of resident tables
-        self.live = {}                          # live id -> _Live
-        self.resident = 0
-        self.next_live = 0
+        self.latest = [None] * len(self.x0)     # (entry, set index) of resident tables
+        self.entries = entries                  # (slot, systems) -> _Entry, least recent first
+        self.resident = sum(e.nbytes for e in entries.values())
         self.kept_inputs = {}
-        self.results = {}                       # rid -> (live id, set index) while resident
-        self.evictions = 0
-        self.host_ms = {"create": [], "stage": [], "launch": [], "wait": [], "release": []}
+        self.results = {}                       # rid -> (entry, set index, launch number)
+        self.evictions = 0                      # systems that lost resident tables
+        self.reused = 0                         # launches that replayed a planned batch
+        self.host_ms = {"create": [], "stage": [], "launch": [], "wait": []}
         torch.cuda.synchronize()
 
     def _step(self, reqs, off, out, stream):
@@ -133,47 +156,52 @@ class Server:
             self.step[r.system] += 1
         self.F.displace(items, self.sigma, out=out, stream=stream)
 
-    def _release(self, lid):
-        e = self.live[lid]
-        e.refs -= 1
-        if e.refs == 0:
-            e.batch.free()
-            self.resident -= e.nbytes
-            del self.live[lid]
-
-    def _evict_oldest(self) -> bool:
-        """Drop the oldest resident batch (all its systems lose their resident
-        tables until their next rebuild). Only called with nothing in flight."""
-        if not self.live:
-            return False
-        lid = min(self.live)
-        e = self.live.pop(lid)
+    def _drop(self, e: _Entry):
+        """Free a planned batch; systems whose tables it held lose them."""
+        del self.entries[(e.slot, e.key)]
         for s, v in enumerate(self.latest):
-            if v is not None and v[0] == lid:
+            if v is not None and v[0] is e:
                 self.latest[s] = None
+                self.evictions += 1
         e.batch.free()
         self.resident -= e.nbytes
-        self.evictions += 1
-        return True
+
+    def _make_room(self, need: int) -> bool:
+        """Free planned batches, least recently used first, until `need`
+        more bytes fit the budget: first those no system's tables live in,
+        then (only with nothing in flight) any idle one. False if it cannot."""
+        for held in (False, True):
+            if held and any(sl.entry is not None for sl in self.slots):
+                break
+            for e in list(self.entries.values()):
+                if self.resident + need <= self.budget:
+                    return True
+                if not e.in_flight and (held or e.refs == 0):
+                    self._drop(e)
+        return self.resident + need <= self.budget
 
     # ------------------------------------------------------------- batches
-    def _launch(self, slot: _Slot, reqs: list, now: float):
+    def _entry_bytes(self, off, lev) -> int:
+        return self.F.batch_footprint(off, lev) + 12 * int(off[-1])
+
+    def _plan(self, si: int, key: tuple, off, lev) -> _Entry:
         torch, F = self.torch, self.F
-        sizes = [self.n[r.system] for r in reqs]
-        off = np.zeros(len(reqs) + 1, dtype=np.uint64)
-        off[1:] = np.cumsum(sizes)
-        lev = np.asarray([self.levels[r.system] for r in reqs], dtype=np.uint8)
+        slot = self.slots[si]
         tc = time.perf_counter()
         b = F.Batch(off, lev, stream=slot.stream)
+        with torch.cuda.stream(slot.stream):
+            xbuf = torch.empty((int(off[-1]), 3), dtype=torch.float32, device="cuda")
+        e = _Entry(key, si, b, xbuf, b.nbytes + 12 * int(off[-1]))
+        self.entries[(si, key)] = e
+        self.resident += e.nbytes
         self.host_ms["create"].append((time.perf_counter() - tc) * 1e3)
+        return e
+
+    def _launch(self, si: int, e: _Entry, reqs: list, off, now: float):
+        torch = self.torch
+        slot = self.slots[si]
         tc = time.perf_counter()
-        total = int(off[-1])
-        if slot.xbuf is None or slot.xbuf.shape[0] < total:
-            # the slot's input buffer: reused once the slot's previous batch is done
-            with torch.cuda.stream(slot.stream):
-                slot.xbuf = torch.empty((max(total, self.max_batch_points), 3),
-                                        dtype=torch.float32, device="cuda")
-        self._step(reqs, off, slot.xbuf, slot.stream)
+        self._step(reqs, off, e.xbuf, slot.stream)
         for r in reqs:
             r.launched = now
             if r.rid in self.keep_inputs:
@@ -181,40 +209,41 @@ class Server:
                     self.kept_inputs[r.rid] = self.x[r.system].clone()
         self.host_ms["stage"].append((time.perf_counter() - tc) * 1e3)
         tc = time.perf_counter()
-        b.launch(slot.xbuf)
+        e.batch.launch(e.xbuf, capture=self.graphs)
         self.host_ms["launch"].append((time.perf_counter() - tc) * 1e3)
         ev = torch.cuda.Event()
         ev.record(slot.stream)
-        slot.batch, slot.event, slot.reqs = b, ev, reqs
-        lid = self.next_live
-        self.next_live += 1
-        self.live[lid] = _Live(b, len(reqs), b.nbytes)
-        self.resident += b.nbytes
-        slot.lid = lid
+        e.in_flight = True
+        e.launches += 1
+        self.entries.move_to_end((si, e.key))
+        slot.entry, slot.event, slot.reqs = e, ev, reqs
 
     def _finish(self, slot: _Slot, t0: float):
+        e = slot.entry
         tc = time.perf_counter()
-        slot.batch.wait()
+        e.batch.wait()
         self.host_ms["wait"].append((time.perf_counter() - tc) * 1e3)
         done = time.perf_counter() - t0
-        lid = slot.lid
+        e.in_flight = False
         for i, r in enumerate(slot.reqs):
             r.done = done
             old = self.latest[r.system]
-            self.latest[r.system] = (lid, i)
-            self.results[r.rid] = (lid, i)
-            if old is not None:
-                tc = time.perf_counter()
-                self._release(old[0])
-                self.host_ms["release"].append((time.perf_counter() - tc) * 1e3)
-        slot.batch, slot.event, slot.reqs = None, None, []
+            if old is None or old[0] is not e:
+                if old is not None:
+                    old[0].refs -= 1
+                e.refs += 1
+            self.latest[r.system] = (e, i)
+            self.results[r.rid] = (e, i, e.launches)
+        slot.entry, slot.event, slot.reqs = None, None, []
 
     def tree_of(self, rid: int):
-        """The tree a request produced, while it is still resident."""
-        lid, i = self.results[rid]
-        if lid not in self.live:
+        """The tree a request produced, while it is still resident (until its
+        system's next request reuses the same planned batch, or the batch is
+        freed for memory)."""
+        e, i, n = self.results[rid]
+        if self.entries.get((e.slot, e.key)) is not e or e.launches != n:
             raise KeyError("tables of this request were replaced")
-        return self.live[lid].batch.tree(i)
+        return e.batch.tree(i)
 
     # ------------------------------------------------------------- loop
     def run(self, arrivals, systems, *, on_complete=None):
@@ -237,7 +266,7 @@ class Server:
                 nxt += 1
             progressed = False
             for slot in self.slots:
-                if slot.batch is not None and slot.event.query():
+                if slot.entry is not None and slot.event.query():
                     fin = slot.reqs
                     self._finish(slot, t0)
                     for r in fin:
@@ -246,9 +275,10 @@ class Server:
                             on_complete(self, r)
                     n_done += len(fin)
                     progressed = True
-            for slot in self.slots:
-                if slot.batch is not None or not pending:
-                    continue
+            while pending:
+                free = [si for si, sl in enumerate(self.slots) if sl.entry is None]
+                if not free:
+                    break
                 take, pts, seen = [], 0, set()
                 for r in pending:
                     if r.system in busy or r.system in seen:
@@ -261,34 +291,44 @@ class Server:
                     pts += self.n[r.system]
                 if not take:
                     break
-                off = np.zeros(len(take) + 1, dtype=np.uint64)
-                off[1:] = np.cumsum([self.n[r.system] for r in take])
-                lev = np.asarray([self.levels[r.system] for r in take], dtype=np.uint8)
-                need = self.F.batch_footprint(off, lev)
-                while len(take) > 1 and self.resident + need > self.budget:
-                    take.pop()  # admit fewer
-                    off = off[:len(take) + 1]
-                    lev = lev[:len(take)]
-                    need = self.F.batch_footprint(off, lev)
-                if self.resident + need > self.budget:
-                    if any(sl.batch is not None for sl in self.slots):
+                e = si = None
+                while True:
+                    # systems in set order: the key of a reusable planned batch,
+                    # on whichever free slot holds one
+                    take.sort(key=lambda r: r.system)
+                    key = tuple(r.system for r in take)
+                    off = np.zeros(len(take) + 1, dtype=np.uint64)
+                    off[1:] = np.cumsum([self.n[r.system] for r in take])
+                    si = next((k for k in free if (k, key) in self.entries), None)
+                    if si is not None:
+                        e = self.entries[(si, key)]
+                        self.reused += 1
+                        break
+                    si = free[0]
+                    lev = np.asarray([self.levels[r.system] for r in take], dtype=np.uint8)
+                    need = self._entry_bytes(off, lev)
+                    if self._make_room(need):
+                        e = self._plan(si, key, off, lev)
+                        break
+                    if len(take) > 1:
+                        take.pop()  # admit fewer
+                        continue
+                    if any(sl.entry is not None for sl in self.slots):
                         break  # wait: a completion will free memory
-                    # Nothing in flight: only evicting resident tables can make room.
-                    while self.resident + need > self.budget and self._evict_oldest():
-                        pass
-                    if self.resident + need > self.budget:
-                        raise self.F.FmmdsError(self.F.ERR_NOMEM,
-                                                f"request {take[0].rid} needs {need} bytes, "
-                                                f"budget {self.budget}")
+                    raise self.F.FmmdsError(self.F.ERR_NOMEM,
+                                            f"request {take[0].rid} needs {need} bytes, "
+                                            f"budget {self.budget}")
+                if e is None:
+                    break
                 for r in take:
                     pending.remove(r)
                     busy.add(r.system)
-                self._launch(slot, take, time.perf_counter() - t0)
+                self._launch(si, e, take, off, time.perf_counter() - t0)
                 progressed = True
             if progressed or (nxt < len(reqs) and not pending):
                 last_progress = time.perf_counter()
             if not progressed:
-                if nxt < len(reqs) and not pending and all(s.batch is None for s in self.slots):
+                if nxt < len(reqs) and not pending and all(s.entry is None for s in self.slots):
                     wait = reqs[nxt].arrival - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.001))
@@ -299,11 +339,14 @@ class Server:
     def close(self):
         self.torch.cuda.synchronize()
         for slot in self.slots:
-            if slot.batch is not None:
-                slot.batch.wait()
-        for e in list(self.live.values()):
+            if slot.entry is not None:
+                slot.entry.batch.wait()
+                slot.entry.in_flight = False
+                slot.entry = None
+        for e in list(self.entries.values()):
             e.batch.free()
-        self.live.clear()
+        self.entries.clear()
+        self.latest = [None] * len(self.x0)
         self.resident = 0
 
 

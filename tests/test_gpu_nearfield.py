@@ -48,6 +48,17 @@ CASES = [
                                   I.uniform_points(125, 30000)[:, 2] - 0.5), 7, 0),
     ("clustered-s64", lambda: (I.sphere_cluster_points(126, 127, 60000), None,
                                I.uniform_points(128, 60000)[:, 0]), 9, 64),
+    # ~15 points per box: most boxes on the dense path with 16 receiver lanes
+    # and 4 source slices per wave, the rest on the sparse path
+    ("mixed-dense-sparse", lambda: (I.uniform_points(161, 60000), I.uniform_points(162, 61000),
+                                    I.uniform_points(163, 60000)[:, 1] - 0.5), 4, 0),
+    # ~100 points per box: two tasks per box, the second a partial one
+    ("dense-multitask", lambda: (I.uniform_points(164, 50000), None,
+                                 I.uniform_points(165, 50000)[:, 2]), 3, 0),
+    # Gaussian clusters at a coarse level: boxes of up to thousands of points
+    ("tight-clusters", lambda: (I.cluster_points(166, 40000, I.cluster_centres(167, 4)),
+                                I.cluster_points(168, 30000, I.cluster_centres(167, 4)),
+                                I.uniform_points(169, 40000)[:, 0]), 5, 0),
 ]
 
 
@@ -134,6 +145,39 @@ def test_full_uniform_2x2p24_L8_sampled(F, oracle_lib):
     rng = np.random.default_rng(9)
     for j in rng.choice(got.size, size=400, replace=False):
         f, a = o.near_field_one(int(j), q)
+        assert abs(float(got[j]) - f) <= (n + 8) * 2.0 ** -24 * a, j
+    g.free()
+    o.close()
+
+
+@pytest.mark.slow
+def test_full_nonuniform_2x2p24_L10_sampled(F, oracle_lib):
+    """The sphere + clusters build (level 10, cluster size 64), where boxes
+    hold up to hundreds of points: receivers sampled uniformly and from the
+    densest receiver boxes against the oracle's per-point definition."""
+    import torch
+    c = I.config_plain_nonuniform()
+    _say("case near field, full nonuniform 2x2^24 L10 s64")
+    g = F.build(parity.to_gpu(c["src"]), parity.to_gpu(c["recv"]), max_level=10, key_bits=64,
+                cluster_s=64)
+    q = I.uniform_points(151, c["src"].shape[0])[:, 1] - 0.5
+    phi, _ = g.near_field(torch.from_numpy(np.ascontiguousarray(q)).cuda())
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    o = oracle_lib.OracleTree(c["src"], c["recv"], key_bits=64, max_level=10, cluster_s=64,
+                              with_lists=False)
+    D = o.depth
+    n = 27 * o.max_occupancy(0, D)
+    rb = o.begin(1, D).astype(np.int64)
+    size = np.diff(rb)
+    perm = o.perm(1)
+    rng = np.random.default_rng(10)
+    dense = np.argsort(-size)[:20]  # the 20 fullest receiver boxes: 10 points of each
+    picks = [int(perm[rb[b] + k]) for b in dense for k in rng.choice(size[b], 10, replace=False)]
+    picks += [int(j) for j in rng.choice(got.size, size=200, replace=False)]
+    _say(f"  {len(picks)} receivers, fullest box {int(size.max())} points")
+    for j in picks:
+        f, a = o.near_field_one(j, q)
         assert abs(float(got[j]) - f) <= (n + 8) * 2.0 ** -24 * a, j
     g.free()
     o.close()

@@ -1,8 +1,9 @@
 """Host logic of the serving loop, on the CPU: with stand-ins for the GPU
-library (a batch's footprint is 10 bytes per point, every launch completes at
-once), the scheduler serves every request, keeps resident memory within the
-budget, evicts under pressure instead of stalling, and rejects a request that
-cannot fit an empty budget."""
+library (a batch's footprint is 10 bytes per point, plus 12 for its input
+buffer; every launch completes at once), the scheduler serves every request,
+keeps resident memory within the budget, evicts under pressure instead of
+stalling, reuses planned batches of the same systems, and rejects a request
+that cannot fit an empty budget."""
 import numpy as np
 import pytest
 
@@ -10,12 +11,15 @@ import paper_1301_1704_amd.serving as S
 
 
 class _Batch:
+    made = 0
+
     def __init__(self, off, lev, stream=None):
         self.nbytes = int(off[-1]) * 10
         self.freed = False
+        _Batch.made += 1
 
-    def launch(self, x):
-        pass
+    def launch(self, x, capture=False):
+        assert not self.freed
 
     def wait(self):
         pass
@@ -120,11 +124,15 @@ def _server(budget, slots=4):
     srv.max_batch_points, srv.max_batch_sets = 1 << 24, 64
     srv.slots = [S._Slot(stream=None) for _ in range(slots)]
     srv.budget, srv.keep_inputs, srv.stall_seconds = budget, set(), 5.0
+    srv.graphs = True
     srv.reset()
     return srv
 
 
-@pytest.mark.parametrize("budget", [10 ** 6, 30000, 9000, 8000])
+PER_POINT = 22  # stand-in footprint (10) + input buffer (12)
+
+
+@pytest.mark.parametrize("budget", [10 ** 6, 66000, 19800, 17600])
 def test_all_requests_served_within_budget(budget):
     arr = np.linspace(0, 0.005, 300)
     pick = np.random.default_rng(1).integers(0, len(SIZES), 300)
@@ -139,7 +147,7 @@ def test_all_requests_served_within_budget(budget):
         per.setdefault(r.system, []).append(r.step)
     for steps in per.values():
         assert steps == sorted(steps) and len(set(steps)) == len(steps)
-    if budget >= sum(SIZES) * 10 * 2:
+    if budget >= sum(SIZES) * PER_POINT * 2:
         assert srv.evictions == 0
     srv.close()
 
@@ -157,7 +165,22 @@ def test_batches_hold_several_requests():
 
 
 def test_oversize_request_rejected():
-    srv = _server(7999)
+    srv = _server(800 * PER_POINT - 1)
     with pytest.raises(_Lib.FmmdsError) as e:
         srv.run(np.zeros(3), np.asarray([7, 0, 1]))
     assert e.value.status == _Lib.ERR_NOMEM
+
+
+def test_repeated_batches_reuse_their_plan():
+    """Four systems on one slot: every batch whose systems were batched
+    together before replays that plan instead of making a new one."""
+    arr = np.linspace(0, 0.002, 80)
+    pick = np.arange(80) % 4
+    srv = _server(10 ** 7, slots=1)
+    made = _Batch.made
+    reqs = srv.run(arr, pick)
+    assert all(r.done >= r.arrival for r in reqs)
+    assert _Batch.made - made == len(srv.entries)
+    launches = len({r.launched for r in reqs})
+    assert srv.reused == launches - len(srv.entries) > 0
+    srv.close()
