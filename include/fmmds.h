@@ -63,7 +63,8 @@ typedef enum fmmds_status {
   FMMDS_ERR_NOMEM = 3,    /* device (or callback) allocation failed */
   FMMDS_ERR_DEVICE = 4,   /* a HIP runtime call failed */
   FMMDS_ERR_LEVEL = 5,    /* list query outside [2, depth] */
-  FMMDS_ERR_OVERFLOW = 6  /* a list at one level would hold 2^32 or more entries */
+  FMMDS_ERR_OVERFLOW = 6, /* a list at one level would hold 2^32 or more entries */
+  FMMDS_ERR_TOO_LARGE = 7 /* the input needs more than an entry point's fixed scratch */
 } fmmds_status;
 
 /* Optional allocator: return `bytes` of device memory usable on `stream`
@@ -348,6 +349,25 @@ fmmds_status fmmds_box_types(const fmmds_tree* t, uint32_t l_par, const uint32_t
  */
 fmmds_status fmmds_near_field(const fmmds_tree* t, const float* charges, float* phi,
                               uint64_t* n_pairs, void* stream);
+
+/*
+ * fmmds_near_field for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, with the scratch (16
+ * bytes per source point for the packed sources, 8 bytes per dense-path task,
+ * at most one task per 9 receiver points, and 256 bytes of counters, each
+ * part rounded up to 256 bytes) in a fixed device array of
+ * FMMDS_NEAR_FIELD_STATIC_BYTES instead of memory from the cache. Each GPU
+ * the library runs on holds its own array until the process ends; the call
+ * allocates nothing. FMMDS_ERR_TOO_LARGE when the scratch would exceed the
+ * array (about 3.9 million source points with as many receivers), otherwise
+ * arguments and errors as fmmds_near_field. Every call on one GPU uses that
+ * GPU's one array and clears what it needs itself: calls that overlap on one
+ * GPU (unordered streams or host threads) race and give wrong results.
+ */
+#define FMMDS_NEAR_FIELD_STATIC_BYTES (64u << 20)
+fmmds_status fmmds_near_field_static(const fmmds_tree* t, const float* charges, float* phi,
+                                     uint64_t* n_pairs, void* stream);
 
 /* Memory the library allocates itself (opt->alloc == NULL) is cached after
  * release, per device, and reused by later builds of similar size. This call

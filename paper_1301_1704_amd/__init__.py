@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmmds.so")
 MAX_LEVEL = 21
 
-OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_LEVEL, ERR_OVERFLOW = range(7)
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_LEVEL, ERR_OVERFLOW, ERR_TOO_LARGE = range(8)
 SRC, RECV = 0, 1
 
 _u32, _u64, _vp = C.c_uint32, C.c_uint64, C.c_void_p
@@ -115,6 +115,8 @@ def _lib():
         L.fmmds_box_types.restype = C.c_int
         L.fmmds_near_field.argtypes = [C.POINTER(TreeStruct), _vp, _vp, _vp, _vp]
         L.fmmds_near_field.restype = C.c_int
+        L.fmmds_near_field_static.argtypes = [C.POINTER(TreeStruct), _vp, _vp, _vp, _vp]
+        L.fmmds_near_field_static.restype = C.c_int
         L.fmmds_displace.argtypes = [C.POINTER(DisplaceSet), _u32, C.c_float, _vp, _vp]
         L.fmmds_displace.restype = C.c_int
         L.fmmds_profile_enable.argtypes = [C.c_int, C.c_char_p]
@@ -140,8 +142,8 @@ def exported_symbols():
             "fmmds_batch_launch", "fmmds_batch_wait", "fmmds_batch_tree",
             "fmmds_batch_footprint", "fmmds_batch_bytes", "fmmds_batch_sort_items",
             "fmmds_batch_free", "fmmds_displace", "fmmds_partition", "fmmds_box_types",
-            "fmmds_near_field", "fmmds_rebuild", "fmmds_build_dense", "fmmds_build_batch",
-            "fmmds_free_batch"]
+            "fmmds_near_field", "fmmds_near_field_static", "fmmds_rebuild", "fmmds_build_dense",
+            "fmmds_build_batch", "fmmds_free_batch"]
 
 
 class DisplaceSet(C.Structure):
@@ -334,11 +336,13 @@ class Tree:
         return out, sizes
 
     # -- near-field sum over E2 (Algorithm 2 with a Laplace kernel)
-    def near_field(self, charges=None, count_pairs: bool = False, stream=None, phi=None):
+    def near_field(self, charges=None, count_pairs: bool = False, stream=None,
+                   phi=None, no_alloc: bool = False):
         """phi per receiver point (original order) as a float32 CUDA tensor,
         and the number of pairs visited (if count_pairs, else None). `phi`:
         an output tensor to fill (float32, n_recv values) instead of a new
-        one."""
+        one. `no_alloc`: fmmds_near_field_static (the library's fixed
+        scratch instead of its cache)."""
         import torch
         s = stream if stream is not None else torch.cuda.current_stream()
         if phi is None:
@@ -352,11 +356,11 @@ class Tree:
                     charges.numel() != self.n_src:
                 raise ValueError("charges: float32 CUDA tensor of n_src values")
             charges = charges.contiguous()
-        st = _lib().fmmds_near_field(self._h, None if charges is None else charges.data_ptr(),
-                                     phi.data_ptr(), None if cnt is None else cnt.data_ptr(),
-                                     s.cuda_stream)
+        fn = _lib().fmmds_near_field_static if no_alloc else _lib().fmmds_near_field
+        st = fn(self._h, None if charges is None else charges.data_ptr(), phi.data_ptr(),
+                None if cnt is None else cnt.data_ptr(), s.cuda_stream)
         if st != OK:
-            raise FmmdsError(st, "fmmds_near_field")
+            raise FmmdsError(st, "fmmds_near_field_static" if no_alloc else "fmmds_near_field")
         return phi, (None if cnt is None else cnt)
 
     # -- host copies (for checks and small consumers)

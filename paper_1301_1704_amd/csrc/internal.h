@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/fmmds.h"
+
 namespace fmmds {
 
 constexpr int kMaxLevel = 21;
@@ -225,6 +227,11 @@ void launch_types_deep(bool key64, const BoxTypeLevel& a, hipStream_t s);
 constexpr uint32_t kNearDenseMin = 8;
 constexpr uint32_t kNearCounters = 2;
 uint64_t near_field_max_tasks(uint32_t n_recv);  // dense-path tasks for n_recv receivers
+// Bytes of the fixed scratch array of the near-field entry point that
+// allocates nothing, and its device address on the current device (looked up
+// once per device). The status is an fmmds_status.
+constexpr size_t kNearStaticBytes = FMMDS_NEAR_FIELD_STATIC_BYTES;
+fmmds_status near_field_static_scratch(void** out);
 void launch_pack_sources(const float* sxyz, const uint32_t* sperm, const float* charges,
                          uint32_t n, float4* out, uint32_t* counters, hipStream_t s);
 void launch_near_field(uint32_t n_rbox, uint32_t n_recv, const uint32_t* rbegin,

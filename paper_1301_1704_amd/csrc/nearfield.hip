@@ -25,6 +25,8 @@
 //     64 / R lane groups (R = r rounded up to a power of two) whose partial
 //     sums are added by shuffles at the end. Waves take tasks from an atomic
 //     ticket until none is left, so boxes of very different sizes balance.
+#include <mutex>
+
 #include "device.h"
 #include "internal.h"
 
@@ -256,6 +258,38 @@ void launch_near_field(uint32_t n_rbox, uint32_t n_recv, const uint32_t* rbegin,
       div_up(near_field_max_tasks(n_recv), waves), 2048);
   hipLaunchKernelGGL(k_near_dense, dim3(grid), dim3(kNearDenseBlock), 0, s, rbegin, rxyz, rperm,
                      e2_off, e2_ent, sbegin, src, phi, n_pairs, tasks, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of fmmds_near_field_static, the entry point for callers that
+// cannot allocate: packed sources, dense-path tasks and counters live here
+// instead of in memory from the cache. Each GPU holds its own copy of the
+// array, at its own address, from the library's load on that GPU until the
+// process ends. In host code `scratch` names a host-side stand-in, never the
+// device memory: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNearStaticBytes];
+
+fmmds_status near_field_static_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return FMMDS_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return FMMDS_ERR_DEVICE;
+    }
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return FMMDS_OK;
 }
 
 }  // namespace fmmds

@@ -1743,6 +1743,19 @@ fmmds_status near_field(const fmmds_tree* t, const float* charges, float* phi,
   return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
 }
 
+// The same kernels on the fixed per-device scratch array: no allocation.
+fmmds_status near_field_static(const fmmds_tree* t, const float* charges, float* phi,
+                               uint64_t* n_pairs, hipStream_t st) {
+  if (!t || !t->impl || !phi) return FMMDS_ERR_ARG;
+  const NearScratch ns(t);
+  if (ns.total > kNearStaticBytes) return FMMDS_ERR_TOO_LARGE;
+  void* scratch = nullptr;
+  const fmmds_status s = near_field_static_scratch(&scratch);
+  if (s != FMMDS_OK) return s;
+  near_field_launch(t, ns, (char*)scratch, charges, phi, n_pairs, st);
+  return hipGetLastError() == hipSuccess ? FMMDS_OK : FMMDS_ERR_DEVICE;
+}
+
 }  // namespace
 }  // namespace fmmds
 
@@ -1892,6 +1905,11 @@ fmmds_status fmmds_near_field(const fmmds_tree* t, const float* charges, float* 
   return fmmds::near_field(t, charges, phi, n_pairs, (hipStream_t)stream);
 }
 
+fmmds_status fmmds_near_field_static(const fmmds_tree* t, const float* charges, float* phi,
+                                     uint64_t* n_pairs, void* stream) {
+  return fmmds::near_field_static(t, charges, phi, n_pairs, (hipStream_t)stream);
+}
+
 void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,
                       uint64_t* cached_bytes) {
   std::lock_guard<std::mutex> g(fmmds::g_cache_mu);
@@ -1961,6 +1979,7 @@ const char* fmmds_status_string(fmmds_status s) {
     case FMMDS_ERR_DEVICE: return "HIP runtime error";
     case FMMDS_ERR_LEVEL: return "level outside [2, depth]";
     case FMMDS_ERR_OVERFLOW: return "list too long for 32-bit offsets";
+    case FMMDS_ERR_TOO_LARGE: return "input larger than the fixed scratch of the entry point";
   }
   return "unknown status";
 }

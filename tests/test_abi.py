@@ -44,7 +44,7 @@ def test_binding_names_match_header():
 
 
 def test_status_strings(lib):
-    for s in range(7):
+    for s in range(8):
         assert lib.fmmds_status_string(s)
     assert lib.fmmds_status_string(2) == b"coordinate outside [0, 1)"
 
