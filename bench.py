@@ -73,11 +73,12 @@ KERNEL_CLASS = [  # rocprofv3 kernel name (namespace and arguments stripped) -> 
     ("k_list_fill", "list_fill"), ("k_list_count", "list_count"),
     ("k_scan_counts2", "scan_counts"), ("k_sort_pass", "sort_pass"), ("k_keygen", "keygen"),
     ("k_digit_offsets", "digit_offsets"), ("k_zero", "zero"), ("k_leaf", "leaf"),
-    ("k_level", "level"), ("k_max_occupancy", "max_occupancy")]
+    ("k_level", "level"), ("k_max_occupancy", "max_occupancy"), ("k_tab_count", "tab_count"),
+    ("k_tab_scan", "tab_scan"), ("k_tab_write", "leaf"), ("k_tab_masks", "level")]
 KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_counts": "lists.hip",
                  "sort_pass": "sort.hip", "keygen": "sort.hip", "digit_offsets": "sort.hip",
                  "zero": "sort.hip", "leaf": "tables.hip", "level": "tables.hip",
-                 "max_occupancy": "tables.hip"}
+                 "max_occupancy": "tables.hip", "tab_count": "tables.hip", "tab_scan": "tables.hip"}
 COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-rebuild "
                 "--no-dense --no-profile --copy-calibration")
 
@@ -575,7 +576,7 @@ def bench_serving(F, torch, args):
             "slots": 4, **{k: v for k, v in head.items() if k != "load"}, "sweep": sweep}
 
 
-PASSES = ("keygen", "sort_pass", "leaf", "level", "scan_counts")
+PASSES = ("keygen", "sort_pass", "tab_count", "tab_scan", "leaf", "level", "scan_counts")
 
 
 def roofline_passes(breakdown: dict, workload_name: str) -> dict:

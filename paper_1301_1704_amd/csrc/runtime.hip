@@ -336,14 +336,16 @@ void fetch_meta(const DevMeta* d, DevMeta* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 enum KernelClass {
   K_ZERO, K_KEYGEN, K_DIGITS, K_SORT, K_LEAF, K_LEVEL, K_MAXOCC, K_COUNT, K_SCAN, K_FILL,
-  K_REBASE, K_CLASSIFY, K_PLACE, K_DCOUNT, K_DSCAN, K_DORDER, K_DLIST, K_NCLASS
+  K_REBASE, K_CLASSIFY, K_PLACE, K_DCOUNT, K_DSCAN, K_DORDER, K_DLIST, K_TCOUNT, K_TSCAN,
+  K_NCLASS
 };
 const char* const kClassName[K_NCLASS] = {"zero",    "keygen",        "digit_offsets",
                                           "sort_pass", "leaf",        "level",
                                           "max_occupancy", "list_count", "scan_counts",
                                           "list_fill",     "batch_rebase", "inc_classify",
                                           "inc_place",     "dense_count",  "dense_scan",
-                                          "dense_order",   "dense_lists"};
+                                          "dense_order",   "dense_lists",  "tab_count",
+                                          "tab_scan"};
 
 struct ClassStat {
   uint64_t launches = 0;
@@ -501,7 +503,6 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       const uint32_t n = sets[s].n;
       const uint32_t np = inc[s] ? inc_pass[s] : n_pass;
       words += (size_t)np * sort_tiles(n, kSortItemsDefault) * 256 + 2 * div_up(n, kCompTile);
-      for (uint32_t l = 0; l < L; ++l) words += div_up(level_cap(n, l + 1), kCompTile);
       tickets += np + 2 + L;
       if (dense) {
         for (uint32_t l = 0; l <= L; ++l) words += dense_scan_tiles(1u << (3 * l));
@@ -650,6 +651,11 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         }
       }
     }
+    // every level's tables in one pass (not the dense variant): per set the
+    // per-tile box-start counts of every level and their scan
+    uint32_t* tabbuf[2] = {nullptr, nullptr};
+    for (int s = 0; !dense && s < nsets; ++s)
+      tabbuf[s] = temps.get<uint32_t>((size_t)2 * (L + 1) * tab_tiles(sets[s].n));
     for (int s = 0; dense && s < nsets; ++s) {
       DenseSet& Dn = dn[s];
       for (uint32_t l = 0; l <= L; ++l) {
@@ -791,27 +797,33 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         fin_v = sb.v[fin];
       }
 
-      // ---- leaf level, then coarser levels
+      // ---- every level's tables from the sorted points
       {
-        uint64_t* stw = sa.take_words(div_up(n, kCompTile));
-        uint32_t* tk = sa.take_ticket();
-        // sorted pairs in, permutation + gathered and written coordinates out;
-        // leaf keys and bookmarks are added once the box count is known
-        P.run(K_LEAF, (double)n * ((packed ? 8 : 12) + 4 + (leaf_xyz ? 12 + 12 : 0)), [&] {
-          launch_leaf(packed, key64, fin_k, fin_v, leaf_xyz, n, S.perm, S.sorted_xyz,
-                      S.lv[L].key, S.lv[L].begin, stw, tk, &meta->n_boxes[s][L], st);
-        }, s, (int)L);
-      }
-      for (int l = (int)L - 1; l >= 0; --l) {
-        LevelBufs& up = S.lv[l];
-        LevelBufs& dn = S.lv[l + 1];
-        uint64_t* stw = sa.take_words(div_up(dn.cap, kCompTile));
-        uint32_t* tk = sa.take_ticket();
-        P.run(K_LEVEL, 0.0, [&] {
-          launch_level(key64, dn.key, dn.begin, &meta->n_boxes[s][l + 1], dn.cap, n, up.key,
-                       up.begin, up.child, up.mask, dn.parent, stw, tk, &meta->n_boxes[s][l],
-                       st);
-        }, s, l);
+        TabLevels T{};
+        for (uint32_t l = 0; l <= L; ++l) {
+          T.key[l] = S.lv[l].key;
+          T.begin[l] = S.lv[l].begin;
+          T.parent[l] = S.lv[l].parent;
+          T.child[l] = S.lv[l].child;
+          T.mask[l] = S.lv[l].mask;
+        }
+        const uint32_t tiles = tab_tiles(n);
+        uint32_t* tcnt = tabbuf[s];
+        uint32_t* tpre = tabbuf[s] + (size_t)(L + 1) * tiles;
+        const double elem_b = packed ? 8 : 12;
+        const double cnt_b = (double)(L + 1) * tiles * 4;
+        uint32_t* nbox = &meta->n_boxes[s][0];
+        auto tab = [&](int phase) {
+          launch_tables(packed, key64, fin_k, fin_v, leaf_xyz, n, L, tcnt, tpre, T, S.perm,
+                        S.sorted_xyz, nbox, L > 0 ? S.lv[L - 1].cap : 0, st, phase);
+        };
+        // sorted elements in, per-tile counts out; the counts scanned; then
+        // (box counts known) the tables, and the child masks
+        P.run(K_TCOUNT, (double)n * elem_b + cnt_b, [&] { tab(0); });
+        P.run(K_TSCAN, 2 * cnt_b, [&] { tab(1); });
+        P.run(K_LEAF, (double)n * (elem_b + 4 + (leaf_xyz ? 12 + 12 : 0)) + cnt_b,
+              [&] { tab(2); }, s, (int)L);
+        P.run(K_LEVEL, 0.0, [&] { tab(3); }, s, -1);
       }
       if (opt->cluster_s > 0) {
         for (uint32_t l = 2; l <= L; ++l) {
@@ -1006,7 +1018,17 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       }
       if (r.set < 0) return 0.0;
       const uint32_t* c = nb[r.set == 0 ? 0 : rs];
-      if (r.cls == K_LEAF) return (double)c[r.level] * (ksz + 4);
+      if (r.cls == K_LEAF) {  // every level: key, bookmark, parent, first child
+        double b = 0;
+        for (uint32_t l = 0; l <= L; ++l)
+          b += (double)c[l] * (ksz + 4 + (l >= 1 ? 4 : 0) + (l < L ? 4 : 0)) + 4 + (l < L ? 4 : 0);
+        return b;
+      }
+      if (r.cls == K_LEVEL && r.level < 0) {  // masks: first children in, children's keys in
+        double b = 0;
+        for (uint32_t l = 0; l < L; ++l) b += (double)c[l] * (4 + 1) + 4 + (double)c[l + 1] * ksz;
+        return b;
+      }
       if (r.cls == K_LEVEL)
         return (double)c[r.level + 1] * (ksz + 4 + 4) + (double)c[r.level] * (ksz + 4 + 4 + 1);
       if (r.cls == K_MAXOCC) return (double)(c[r.level] + 1) * 4;
