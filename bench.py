@@ -74,11 +74,15 @@ KERNEL_CLASS = [  # rocprofv3 kernel name (namespace and arguments stripped) -> 
     ("k_scan_counts2", "scan_counts"), ("k_sort_pass", "sort_pass"), ("k_keygen", "keygen"),
     ("k_digit_offsets", "digit_offsets"), ("k_zero", "zero"), ("k_leaf", "leaf"),
     ("k_level", "level"), ("k_max_occupancy", "max_occupancy"), ("k_tab_count", "tab_count"),
-    ("k_tab_scan", "tab_scan"), ("k_tab_write", "leaf"), ("k_tab_masks", "level")]
+    ("k_tab_scan", "tab_scan"), ("k_tab_write", "leaf"), ("k_tab_masks", "level"),
+    ("k_pack_sources", "near_pack"), ("k_near_field", "near_sparse"),
+    ("k_near_dense", "near_dense")]
 KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_counts": "lists.hip",
                  "sort_pass": "sort.hip", "keygen": "sort.hip", "digit_offsets": "sort.hip",
                  "zero": "sort.hip", "leaf": "tables.hip", "level": "tables.hip",
-                 "max_occupancy": "tables.hip", "tab_count": "tables.hip", "tab_scan": "tables.hip"}
+                 "max_occupancy": "tables.hip", "tab_count": "tables.hip", "tab_scan": "tables.hip",
+                 "near_pack": "nearfield.hip", "near_sparse": "nearfield.hip",
+                 "near_dense": "nearfield.hip"}
 COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-rebuild "
                 "--no-dense --no-profile --copy-calibration")
 

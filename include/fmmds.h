@@ -159,6 +159,10 @@ fmmds_status fmmds_build_dense(const float* src_xyz, uint32_t n_src, const float
  *             row j is original point j (as for fmmds_build); with 1, row k
  *             is the point at prev's sorted position k, i.e. original point
  *             prev->src_perm[k] (e.g. prev->src_sorted_xyz after moving).
+ *             Only positions in prev's order are rebuilt incrementally: with
+ *             in_prev_order == 0 the call builds from scratch (bringing the
+ *             positions into prev's order is a random read per point, which
+ *             costs more than the sort it would save), with the same result.
  *   recv_xyz: device, 3 * prev->n_recv values in the same order convention,
  *             or NULL iff prev->shared.
  *   opt:      host; max_level must equal prev->max_level (the sort key);
@@ -238,7 +242,9 @@ fmmds_status fmmds_batch_footprint(const uint64_t* set_offsets, const uint8_t* l
                                    uint32_t n_sets, uint64_t* bytes);
 /* Device bytes the batch holds. */
 uint64_t fmmds_batch_bytes(const fmmds_batch* b);
-/* Sort tile size (elements per thread: 8, 12 or 16) the batch uses. */
+/* Sort tile size the batch uses, in units of 256 elements: 8, 12 or 16
+ * (tiles of 256 threads with that many elements each) or 32 (8192 elements,
+ * 512 threads). */
 uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
 void fmmds_batch_free(fmmds_batch* b);
 

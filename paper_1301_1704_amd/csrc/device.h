@@ -57,6 +57,15 @@ __device__ __forceinline__ uint64_t point_key(float x, float y, float z, uint32_
   return spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
 }
 
+// Blocks are dispatched to the 8 XCDs (each with its own L2) round-robin:
+// block b runs on XCD b % 8. Renumbering so that each XCD takes one
+// contiguous range of work keeps each XCD's reads and writes in one region
+// of memory. A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, q = n >> 3, r = n & 7u;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // Wave64 primitives.
 // ---------------------------------------------------------------------------

@@ -13,7 +13,11 @@ constexpr int kMaxPasses = 8;  // 63 key bits / 8-bit digits
 
 // Tile shapes of the single-pass kernels.
 constexpr int kSortBlock = 256;
-constexpr int kSortItemsDefault = 16;  // tile = 256 * items elements (8, 12 or 16)
+// Sort tile sizes, in units of 256 elements: 8, 12 and 16 are tiles of
+// 256 threads with that many elements each; kSortWide is a tile of 8192
+// elements (512 threads x 16), for packed elements only.
+constexpr int kSortItemsDefault = 16;
+constexpr int kSortWide = 32;
 constexpr int kCompBlock = 256;
 constexpr int kCompItems = 8;
 constexpr int kCompTile = kCompBlock * kCompItems;  // 2048 elements
@@ -123,12 +127,11 @@ void launch_scan_counts2(const uint32_t* cnt2, const uint32_t* cnt4, uint32_t n,
                          hipStream_t s, const uint32_t* n_dev = nullptr);
 
 // ---- rebuild.hip
-void launch_inc_classify(const float* xyz, bool prev_order, const float* old_xyz,
-                         const uint32_t* old_perm, uint32_t n, uint32_t L, uint32_t ib,
-                         uint32_t n_pass, uint64_t* st_v, uint32_t* st_slot, uint64_t* mv_v,
-                         uint32_t* mv_slot, uint32_t* hist, uint32_t* err, uint64_t* status,
-                         uint32_t* tile_counter, uint32_t* counts, float* staged,
-                         hipStream_t s);  // staged: 3 n floats, written unless prev_order
+void launch_inc_classify(const float* xyz, const float* old_xyz, const uint32_t* old_perm,
+                         uint32_t n, uint32_t L, uint32_t ib, uint32_t n_pass, uint64_t* st_v,
+                         uint32_t* st_slot, uint64_t* mv_v, uint32_t* mv_slot, uint32_t* hist,
+                         uint32_t* err, uint64_t* status, uint32_t* tile_counter,
+                         uint32_t* counts, hipStream_t s);  // xyz in the previous sorted order  // staged: 3 n floats, written unless prev_order
 void launch_inc_scatter(const float* xyz, const uint32_t* old_perm, uint32_t n, float* out,
                         hipStream_t s);
 void launch_inc_merge(bool packed, const uint64_t* st_v, const uint32_t* st_slot, uint32_t ns,

@@ -54,14 +54,6 @@ __device__ __forceinline__ int axis_delta(A sk, A pk, A axis_mask, A axis_low) {
   return d == 0 ? 0 : (d == axis_low ? 1 : -1);
 }
 
-// Blocks are dispatched to the 8 XCDs (each with its own L2) round-robin:
-// block b runs on XCD b % 8. Renumbering so that each XCD takes one
-// contiguous range of work keeps each XCD's reads and writes in one region
-// of memory. A bijection on [0, n).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
-  const uint32_t x = b & 7u, q = n >> 3, r = n & 7u;
-  return x * q + min(x, r) + (b >> 3);
-}
 
 // Inclusive scan within each 32-lane half of the wave.
 __device__ __forceinline__ uint32_t half_incl_scan(uint32_t v) {
@@ -421,16 +413,20 @@ void launch_list_fill(bool key64, const ListLevelArgs& a, const uint32_t* off2,
 // Each thread owns 16 consecutive boxes, read and written with 16-byte
 // accesses (both count arrays and both offset arrays start 16-byte aligned).
 // ---------------------------------------------------------------------------
+// 1024 threads x 16 counts per tile: a quarter of the tiles (and of the
+// look-back chain) of 256-thread tiles; the largest scan (10.6M boxes) took
+// 98 us with 4096-count tiles.
+constexpr int kScanBlock = 1024;
 constexpr int kScanItems = 16;
-constexpr int kScanTile = kCompBlock * kScanItems;  // 4096 boxes
+constexpr int kScanTile = kScanBlock * kScanItems;  // 16384 boxes
 
-__global__ __launch_bounds__(kCompBlock) void k_scan_counts2(
+__global__ __launch_bounds__(kScanBlock) void k_scan_counts2(
     const uint32_t* __restrict__ cnt2, const uint32_t* __restrict__ cnt4, uint32_t n_host,
     const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ off2, uint32_t* __restrict__ off4,
     uint64_t* __restrict__ total2, uint64_t* __restrict__ total4, uint32_t* __restrict__ overflow,
     uint64_t* __restrict__ status2, uint64_t* __restrict__ status4,
     uint32_t* __restrict__ tile_counter) {
-  __shared__ uint32_t s_w[2][kCompBlock / 64];
+  __shared__ uint32_t s_w[2][kScanBlock / 64];
   __shared__ uint64_t s_excl[2];
   __shared__ uint32_t s_tile;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -471,7 +467,7 @@ __global__ __launch_bounds__(kCompBlock) void k_scan_counts2(
   }
   __syncthreads();
   uint32_t wpre2 = 0, wpre4 = 0, tot2 = 0, tot4 = 0;
-  for (uint32_t i = 0; i < kCompBlock / 64; ++i) {
+  for (uint32_t i = 0; i < kScanBlock / 64; ++i) {
     if (i < w) {
       wpre2 += s_w[0][i];
       wpre4 += s_w[1][i];
@@ -536,7 +532,7 @@ void launch_scan_counts2(const uint32_t* cnt2, const uint32_t* cnt4, uint32_t n,
                          hipStream_t s, const uint32_t* n_dev) {
   // n is the exact count, or with n_dev the capacity (the count is read there)
   if (n == 0) return;
-  hipLaunchKernelGGL(k_scan_counts2, dim3(scan_tiles(n)), dim3(kCompBlock), 0, s, cnt2, cnt4, n,
+  hipLaunchKernelGGL(k_scan_counts2, dim3(scan_tiles(n)), dim3(kScanBlock), 0, s, cnt2, cnt4, n,
                      n_dev, off2, off4, total2, total4, overflow, status2, status4, tile_counter);
 }
 

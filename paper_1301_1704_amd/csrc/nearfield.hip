@@ -23,8 +23,8 @@
 //     coalesced 16-byte load per lane) and every lane sums its receiver
 //     against the whole tile. A task of r < 64 receivers splits the tile over
 //     64 / R lane groups (R = r rounded up to a power of two) whose partial
-//     sums are added by shuffles at the end. Waves take tasks from an atomic
-//     ticket until none is left, so boxes of very different sizes balance.
+//     sums are added by shuffles at the end. After its first task a wave takes
+//     the next from an atomic ticket, so boxes of very different sizes balance.
 #include <mutex>
 
 #include "device.h"
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_near_field(
   }
 }
 
-// Dense path: one wave per task, waves taking tasks from a ticket. Lane l
+// Dense path: one wave per task, waves taking further tasks from a ticket. Lane l
 // first loads E2 entry l of the box (lists hold at most 27 entries) and the
 // entries' point counts are scanned across the wave, so that the box's
 // source points form one concatenated sequence; each round stages the next
@@ -155,12 +155,12 @@ __global__ __launch_bounds__(kNearDenseBlock) void k_near_dense(
   __shared__ uint32_t s_first[kWaves][64];  // first sorted source point of each entry
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   const uint32_t n_tasks = __hip_atomic_load(&counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t n_waves = gridDim.x * kWaves;
   uint64_t pairs = 0;
-  while (true) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&counters[1], 1u);
-    t = __shfl(t, 0, 64);
-    if (t >= n_tasks) break;
+  // Wave g takes task g first, then tickets past the first n_waves: waves
+  // without a task exit without touching the ticket (atomics on one address
+  // are serialized, and most waves have nothing to do on sparse input).
+  for (uint32_t t = blockIdx.x * kWaves + w; t < n_tasks;) {
     const uint2 task = tasks[t];
     const uint32_t b = task.x;
     const uint32_t k0 = rbegin[b] + 64u * task.y;
@@ -224,6 +224,9 @@ __global__ __launch_bounds__(kNearDenseBlock) void k_near_dense(
     // the next task restages s_pre / s_first: all reads of this one are done
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(&counters[1], 1u);
+    t = n_waves + __shfl(next, 0, 64);
   }
   if (n_pairs && lane == 0 && pairs) atomicAdd(n_pairs, (unsigned long long)pairs);
 }

@@ -31,20 +31,18 @@ struct P3 {
 
 constexpr int kClsWaves = kCompBlock / 64;
 
-// Classification: tiles of kCompTile slots in slot order (positions given in
-// original order are gathered through the old permutation once and written
-// out in slot order, so that the merge reads them in order); a stayer goes to
-// the stayer list at its rank among stayers, a mover to the mover list at its
-// rank among movers (slot minus stayers before it); both lists keep slot
-// order. One chained scan over the tiles counts the stayers. The digit
-// histograms of the movers' merge values feed their sort.
-template <bool PREV_ORDER>
+// Classification: tiles of kCompTile slots in slot order (the new positions
+// are given in the previous sorted order); a stayer goes to the stayer list
+// at its rank among stayers, a mover to the mover list at its rank among
+// movers (slot minus stayers before it); both lists keep slot order. One
+// chained scan over the tiles counts the stayers. The digit histograms of
+// the movers' merge values feed their sort.
 __global__ __launch_bounds__(kCompBlock) void k_inc_classify(
     const P3* __restrict__ xyz, const P3* __restrict__ old_xyz, const uint32_t* __restrict__ old_perm,
     uint32_t n, uint32_t L, uint32_t ib, uint32_t n_pass, uint64_t* __restrict__ st_v,
     uint32_t* __restrict__ st_slot, uint64_t* __restrict__ mv_v, uint32_t* __restrict__ mv_slot,
     uint32_t* __restrict__ hist, uint32_t* __restrict__ err, uint64_t* __restrict__ status,
-    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ counts, P3* __restrict__ staged) {
+    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ counts) {
   __shared__ uint32_t s_cnt[kCompItems * kClsWaves];
   __shared__ uint32_t s_hist[kMaxPasses * 256];
   __shared__ uint64_t s_excl;
@@ -64,11 +62,7 @@ __global__ __launch_bounds__(kCompBlock) void k_inc_classify(
     const uint64_t ec = min<uint64_t>(tbase + (uint64_t)i * kCompBlock + tid, n - 1);
     idx[i] = old_perm[ec];
     po[i] = old_xyz[ec];
-    if (PREV_ORDER) pn[i] = xyz[ec];
-  }
-  if (!PREV_ORDER) {
-#pragma unroll
-    for (int i = 0; i < kCompItems; ++i) pn[i] = xyz[idx[i]];
+    pn[i] = xyz[ec];
   }
   uint64_t v[kCompItems];
   uint32_t incl[kCompItems];
@@ -97,7 +91,6 @@ __global__ __launch_bounds__(kCompBlock) void k_inc_classify(
   for (int i = 0; i < kCompItems; ++i) {
     const uint64_t e = tbase + (uint64_t)i * kCompBlock + tid;
     if (e >= n) continue;
-    if (!PREV_ORDER) staged[e] = pn[i];  // the gathered positions, in slot order
     const uint64_t st_incl = texcl + s_cnt[i * kClsWaves + w] + incl[i];  // stayers in [0, e]
     if ((stay >> i) & 1u) {
       st_v[st_incl - 1] = v[i];
@@ -294,21 +287,15 @@ void launch_inc_scatter(const float* xyz, const uint32_t* old_perm, uint32_t n, 
                      (P3*)out);
 }
 
-void launch_inc_classify(const float* xyz, bool prev_order, const float* old_xyz,
-                         const uint32_t* old_perm, uint32_t n, uint32_t L, uint32_t ib,
-                         uint32_t n_pass, uint64_t* st_v, uint32_t* st_slot, uint64_t* mv_v,
-                         uint32_t* mv_slot, uint32_t* hist, uint32_t* err, uint64_t* status,
-                         uint32_t* tile_counter, uint32_t* counts, float* staged,
-                         hipStream_t s) {
+void launch_inc_classify(const float* xyz, const float* old_xyz, const uint32_t* old_perm,
+                         uint32_t n, uint32_t L, uint32_t ib, uint32_t n_pass, uint64_t* st_v,
+                         uint32_t* st_slot, uint64_t* mv_v, uint32_t* mv_slot, uint32_t* hist,
+                         uint32_t* err, uint64_t* status, uint32_t* tile_counter,
+                         uint32_t* counts, hipStream_t s) {
   const uint32_t grid = div_up(n, kCompTile);
-  if (prev_order)
-    hipLaunchKernelGGL(k_inc_classify<true>, dim3(grid), dim3(kCompBlock), 0, s, (const P3*)xyz,
-                       (const P3*)old_xyz, old_perm, n, L, ib, n_pass, st_v, st_slot, mv_v,
-                       mv_slot, hist, err, status, tile_counter, counts, (P3*)staged);
-  else
-    hipLaunchKernelGGL(k_inc_classify<false>, dim3(grid), dim3(kCompBlock), 0, s, (const P3*)xyz,
-                       (const P3*)old_xyz, old_perm, n, L, ib, n_pass, st_v, st_slot, mv_v,
-                       mv_slot, hist, err, status, tile_counter, counts, (P3*)staged);
+  hipLaunchKernelGGL(k_inc_classify, dim3(grid), dim3(kCompBlock), 0, s, (const P3*)xyz,
+                     (const P3*)old_xyz, old_perm, n, L, ib, n_pass, st_v, st_slot, mv_v, mv_slot,
+                     hist, err, status, tile_counter, counts);
 }
 
 void launch_inc_merge(bool packed, const uint64_t* st_v, const uint32_t* st_slot, uint32_t ns,

@@ -429,11 +429,10 @@ struct Prof {
 uint32_t index_bits(uint32_t n) { return n <= 2 ? 1u : 32u - (uint32_t)__builtin_clz(n - 1); }
 
 // prev: with a previous tree, the order is rebuilt incrementally from it
-// (prev_order: the coordinates are given in prev's sorted order).
+// (the coordinates are given in prev's sorted order).
 fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, uint32_t n_recv,
                    const fmmds_options* opt, fmmds_tree** out,
-                   const fmmds_tree* prev = nullptr, bool prev_order = false,
-                   bool dense = false) {
+                   const fmmds_tree* prev = nullptr, bool dense = false) {
   const bool shared = recv_xyz == nullptr;
   if (shared) n_recv = n_src;
   if (!src_xyz || !opt || n_src == 0 || n_recv == 0 || n_src >= 0xFFFFFFFFu ||
@@ -549,7 +548,6 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     uint64_t* inc_mv[2] = {sb.k[0], sb.k[0]};
     uint32_t* inc_ms[2] = {sb.v[0], sb.v[0]};
     uint32_t n_stay[2] = {0, 0}, n_move[2] = {0, 0};
-    float* staged[2] = {nullptr, nullptr};  // original-order positions, gathered in slot order
     if (prev) {
       bool any = false;
       for (int s = 0; s < nsets; ++s) {
@@ -562,14 +560,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           inc_sv[1] = temps.get<uint64_t>(n);
           inc_ss[1] = temps.get<uint32_t>(n);
         }
-        if (!prev_order) staged[s] = temps.get<float>(3 * (size_t)n);
         uint64_t* stw = sa.take_words(div_up(n, kCompTile));
         uint32_t* tk = sa.take_ticket();
-        P.run(K_CLASSIFY, (double)n * (4 + 12 + 12 + 12 + (prev_order ? 0 : 12)), [&] {
-          launch_inc_classify(sets[s].xyz, prev_order, old_xyz[s], old_perm[s], n, L, ibits[s],
+        P.run(K_CLASSIFY, (double)n * (4 + 12 + 12 + 12), [&] {
+          launch_inc_classify(sets[s].xyz, old_xyz[s], old_perm[s], n, L, ibits[s],
                               inc_pass[s], inc_sv[s], inc_ss[s], inc_mv[s], inc_ms[s],
                               hist + s * kMaxPasses * 256, &meta->err_range, stw, tk,
-                              meta->inc_counts[s], staged[s], st);
+                              meta->inc_counts[s], st);
         });
       }
       if (any) {
@@ -616,7 +613,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       }
     }
     for (int s = 0; s < nsets; ++s)
-      if (prev && prev_order && !inc[s]) full_x[s] = temps.get<float>(3 * (size_t)sets[s].n);
+      if (prev && !inc[s]) full_x[s] = temps.get<float>(3 * (size_t)sets[s].n);
     for (int s = 0; s < nsets; ++s) {
       SetBufs& S = sets[s];
       const uint32_t n = S.n;
@@ -761,14 +758,14 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         const int mf = nm > 0 ? (int)(np & 1) : 0;
         P.run(K_PLACE, (double)n * (8 + 4 + 12 + 8 + (packed ? 0 : 4) + 12), [&] {
           launch_inc_merge(packed, inc_sv[s], inc_ss[s], n_stay[s], mk[mf], mv[mf], nm,
-                           prev_order ? S.xyz : staged[s], ib, inc_fk, inc_fv, S.sorted_xyz,
+                           S.xyz, ib, inc_fk, inc_fv, S.sorted_xyz,
                            st);
         });
         fin_k = inc_fk;
         fin_v = inc_fv;
         leaf_xyz = nullptr;
       } else {
-        if (prev && prev_order) {
+        if (prev) {
           // the merge value does not fit: full sort, from original order
           float* x = full_x[s];
           P.run(K_PLACE, 0.0, [&] { launch_inc_scatter(S.xyz, old_perm[s], n, x, st); });
@@ -789,7 +786,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
           uint32_t* tk = sa.take_ticket();
           P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
             launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,
-                             stw, tk, st, kSortItemsDefault);
+                             stw, tk, st, packed ? kSortWide : kSortItemsDefault);
           });
         }
         const int fin = n_pass & 1;
@@ -1308,7 +1305,8 @@ int batch_autotune(BatchImpl& B, const float* xyz) {
   ck(hipEventCreate(&e1));
   int best = kSortItemsDefault;
   float best_ms = 1e30f;
-  for (int items : {8, 12, 16}) {
+  for (int items : {8, 12, 16, kSortWide}) {
+    if (items == kSortWide && !B.packed) continue;
     float total = 0;
     for (int rep = 0; rep < 2; ++rep) {
       StatusArena sa;
@@ -1799,15 +1797,20 @@ fmmds_status fmmds_rebuild(const fmmds_tree* prev, const float* src_xyz, const f
   if (opt->max_level != prev->max_level) return FMMDS_ERR_ARG;
   if (!prev->src_perm || !prev->src_sorted_xyz || !prev->recv_perm || !prev->recv_sorted_xyz)
     return FMMDS_ERR_ARG;
-  return fmmds::build(src_xyz, prev->n_src, recv_xyz, prev->n_recv, opt, out, prev,
-                      in_prev_order != 0);
+  // Positions in the original order: the incremental path would first
+  // gather them into the previous order, a random 12-byte read per point,
+  // which costs more than the full sort it saves; the fresh build returns the
+  // same tree.
+  if (in_prev_order == 0)
+    return fmmds::build(src_xyz, prev->n_src, recv_xyz, prev->n_recv, opt, out);
+  return fmmds::build(src_xyz, prev->n_src, recv_xyz, prev->n_recv, opt, out, prev);
 }
 
 fmmds_status fmmds_build_dense(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
                                uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out) {
   if (!out) return FMMDS_ERR_ARG;
   *out = nullptr;
-  return fmmds::build(src_xyz, n_src, recv_xyz, n_recv, opt, out, nullptr, false, true);
+  return fmmds::build(src_xyz, n_src, recv_xyz, n_recv, opt, out, nullptr, true);
 }
 
 fmmds_status fmmds_neighbors(const fmmds_tree* t, uint32_t level, const uint32_t** offsets,

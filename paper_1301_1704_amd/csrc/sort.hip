@@ -40,6 +40,12 @@ struct P3 {
   float x, y, z;
 };
 
+// Each thread loads kKeyItems points (one 64-point run per wave and item,
+// all issued before any is used), so the loads of a block are in flight
+// together rather than one per loop trip.
+constexpr int kKeyItems = 8;
+constexpr int kKeyChunk = 256 * kKeyItems;
+
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint32_t n, uint32_t L,
                                                 uint64_t* __restrict__ keys,
@@ -50,19 +56,30 @@ __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
   __syncthreads();
   bool bad = false;
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
-    const P3 p = xyz[i];
-    bool ok;
-    const uint64_t key = point_key(p.x, p.y, p.z, L, ok);
-    bad |= !ok;
-    if (PACKED) {
-      keys[i] = (key << 32) | (uint32_t)i;
-    } else {
-      keys[i] = key;
-      vals[i] = (uint32_t)i;
+  for (uint64_t base = (uint64_t)blockIdx.x * kKeyChunk; base < n;
+       base += (uint64_t)gridDim.x * kKeyChunk) {
+    P3 p[kKeyItems];
+#pragma unroll
+    for (int j = 0; j < kKeyItems; ++j) {
+      const uint64_t i = base + (uint64_t)j * 256 + threadIdx.x;
+      p[j] = i < n ? xyz[i] : P3{0.f, 0.f, 0.f};
     }
-    for (uint32_t p8 = 0; p8 < n_pass; ++p8)
-      atomicAdd(&s_hist[p8 * 256 + ((key >> (8 * p8)) & 0xFF)], 1u);
+#pragma unroll
+    for (int j = 0; j < kKeyItems; ++j) {
+      const uint64_t i = base + (uint64_t)j * 256 + threadIdx.x;
+      if (i >= n) continue;
+      bool ok;
+      const uint64_t key = point_key(p[j].x, p[j].y, p[j].z, L, ok);
+      bad |= !ok;
+      if (PACKED) {
+        keys[i] = (key << 32) | (uint32_t)i;
+      } else {
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
+      }
+      for (uint32_t p8 = 0; p8 < n_pass; ++p8)
+        atomicAdd(&s_hist[p8 * 256 + ((key >> (8 * p8)) & 0xFF)], 1u);
+    }
   }
   if (bad) atomicOr(err, 1u);
   __syncthreads();
@@ -73,7 +90,7 @@ __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint
 void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
                    uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
                    hipStream_t s) {
-  const uint32_t grid = std::min<uint32_t>(div_up(n, 256), 2048);
+  const uint32_t grid = std::min<uint32_t>(div_up(n, kKeyChunk), 2048);
   if (packed)
     hipLaunchKernelGGL(k_keygen<true>, dim3(grid), dim3(256), 0, s, (const P3*)xyz, n, L, keys,
                        vals, n_pass, hist, err);
@@ -103,37 +120,40 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 // ---------------------------------------------------------------------------
 // K2: one stable LSD pass on the 8-bit digit at `shift`.
 //
-// A tile of 4096 elements is split into four contiguous 1024-element wave
-// segments, loaded 64 at a time (coalesced). Each wave ranks its elements by
-// digit with eight ballots per element (lanes whose digit agrees on every
-// bit), keeping running per-digit counts in LDS, so ranks follow input order.
-// The tile's 256 digit counts are then chained across tiles by decoupled
-// look-back (thread d owns digit d), the tile is staged in LDS in digit order,
-// and written out so that consecutive threads store consecutive addresses of
-// one digit's run.
+// A tile of BLOCK * ITEMS elements is split into contiguous 64 * ITEMS-element
+// wave segments, loaded 64 at a time (coalesced). Each wave ranks its
+// elements by digit with eight ballots per element (lanes whose digit agrees
+// on every bit), keeping running per-digit counts in LDS, so ranks follow
+// input order. The tile's 256 digit counts are then chained across tiles by
+// decoupled look-back (thread d < 256 owns digit d), the tile is staged in
+// LDS in digit order, and written out so that consecutive threads store
+// consecutive addresses of one digit's run. Tiles of 8192 packed elements
+// (512 threads) halve the chain of look-backs of 4096-element tiles, which
+// is what sets the pass's length: without its look-back a 4096-element pass
+// over 2^24 elements takes ~75 us instead of ~125 us.
 // ---------------------------------------------------------------------------
-constexpr int kSortWaves = kSortBlock / 64;
-
-template <bool PACKED, int ITEMS>
-__global__ __launch_bounds__(kSortBlock) void k_sort_pass(
+template <bool PACKED, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_sort_pass(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ vout, uint32_t n_host, uint32_t shift, const uint32_t* __restrict__ goff,
     uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
     const uint32_t* __restrict__ n_dev) {
-  constexpr int TILE = kSortBlock * ITEMS;
+  static_assert(BLOCK >= 256, "thread d owns digit d");
+  constexpr int W = BLOCK / 64;
+  constexpr int TILE = BLOCK * ITEMS;
   constexpr int WSEG = 64 * ITEMS;
   __shared__ uint64_t s_key[TILE];
   __shared__ uint32_t s_val[PACKED ? 1 : TILE];
-  __shared__ uint32_t s_hist[kSortWaves][256];
+  __shared__ uint32_t s_hist[W][256];
   __shared__ uint32_t s_lstart[256];
   __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_scan[kSortWaves];
+  __shared__ uint32_t s_scan[4];
   __shared__ uint32_t s_tile;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-  for (uint32_t i = tid; i < kSortWaves * 256; i += kSortBlock) (&s_hist[0][0])[i] = 0;
+  for (uint32_t i = tid; i < W * 256; i += BLOCK) (&s_hist[0][0])[i] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
   // With the count on the device the grid covers the capacity; tiles past
@@ -169,25 +189,31 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   }
   __syncthreads();
 
-  // Thread tid owns digit tid: wave-exclusive prefixes, tile count, local start.
-  const uint32_t d = tid;
-  uint32_t run = 0;
+  // Thread d < 256 owns digit d: wave-exclusive prefixes, tile count, local
+  // start, then the tile's global base by look-back.
+  uint32_t cnt = 0, inc = 0;
+  if (tid < 256) {
+    uint32_t run = 0;
 #pragma unroll
-  for (int ww = 0; ww < kSortWaves; ++ww) {
-    const uint32_t c = s_hist[ww][d];
-    s_hist[ww][d] = run;
-    run += c;
+    for (int ww = 0; ww < W; ++ww) {
+      const uint32_t c = s_hist[ww][tid];
+      s_hist[ww][tid] = run;
+      run += c;
+    }
+    cnt = run;
+    inc = wave_incl_scan(cnt);
+    if (lane == 63) s_scan[w] = inc;
   }
-  const uint32_t cnt = run;
-  const uint32_t inc = wave_incl_scan(cnt);
-  if (lane == 63) s_scan[w] = inc;
   __syncthreads();
-  uint32_t wpre = 0;
-  for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
-  const uint32_t lstart = wpre + inc - cnt;
-  s_lstart[d] = lstart;
-  const uint64_t excl = lookback(status + d, 256, tile, cnt);
-  s_base[d] = goff[d] + (uint32_t)excl - lstart;
+  if (tid < 256) {
+    const uint32_t d = tid;
+    uint32_t wpre = 0;
+    for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
+    const uint32_t lstart = wpre + inc - cnt;
+    s_lstart[d] = lstart;
+    const uint64_t excl = lookback(status + d, 256, tile, cnt);
+    s_base[d] = goff[d] + (uint32_t)excl - lstart;
+  }
   __syncthreads();
 
 #pragma unroll
@@ -202,7 +228,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   __syncthreads();
   const uint64_t tbase = (uint64_t)tile * TILE;
   const uint32_t tcount = (uint32_t)min((uint64_t)TILE, (uint64_t)n - tbase);
-  for (uint32_t j = tid; j < tcount; j += kSortBlock) {
+  for (uint32_t j = tid; j < tcount; j += BLOCK) {
     const uint64_t kk = s_key[j];
     const uint32_t dd = (uint32_t)(kk >> shift) & 0xFFu;
     const uint32_t g = s_base[dd] + j;
@@ -211,25 +237,28 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
   }
 }
 
-uint32_t sort_tiles(uint32_t n, int items) { return div_up(n, (uint64_t)kSortBlock * items); }
+uint32_t sort_tile_elems(int items) { return items == kSortWide ? 8192u : 256u * (uint32_t)items; }
+
+uint32_t sort_tiles(uint32_t n, int items) { return div_up(n, sort_tile_elems(items)); }
 
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
                       uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
                       const uint32_t* n_dev) {
   const uint32_t grid = sort_tiles(n, items);
-#define FMMDS_SORT(P, I)                                                                        \
-  hipLaunchKernelGGL((k_sort_pass<P, I>), dim3(grid), dim3(kSortBlock), 0, s, kin, kout, vin,  \
-                     vout, n, shift, goff, status, tile_counter, n_dev)
-  if (items == 8) {
-    if (packed) FMMDS_SORT(true, 8);
-    else FMMDS_SORT(false, 8);
+#define FMMDS_SORT(P, B, I)                                                                     \
+  hipLaunchKernelGGL((k_sort_pass<P, B, I>), dim3(grid), dim3(B), 0, s, kin, kout, vin, vout,  \
+                     n, shift, goff, status, tile_counter, n_dev)
+  if (items == kSortWide && packed) FMMDS_SORT(true, 512, 16);
+  else if (items == 8) {
+    if (packed) FMMDS_SORT(true, 256, 8);
+    else FMMDS_SORT(false, 256, 8);
   } else if (items == 12) {
-    if (packed) FMMDS_SORT(true, 12);
-    else FMMDS_SORT(false, 12);
+    if (packed) FMMDS_SORT(true, 256, 12);
+    else FMMDS_SORT(false, 256, 12);
   } else {
-    if (packed) FMMDS_SORT(true, 16);
-    else FMMDS_SORT(false, 16);
+    if (packed) FMMDS_SORT(true, 256, 16);
+    else FMMDS_SORT(false, 256, 16);
   }
 #undef FMMDS_SORT
 }

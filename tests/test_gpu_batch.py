@@ -110,11 +110,11 @@ def test_batch_graph_replay(F):
     ref = {i: [eager.tree(i).host_list(k, int(lev[i])) for k in (2, 4)] + [eager.tree(i).host_perm(0)]
            for i in range(0, 24, 5)}
     g = F.Batch(off, lev)
-    assert g.sort_items in (8, 12, 16)
+    assert g.sort_items in (8, 12, 16, 32)
     for rep in range(4):
         g.launch(x, capture=True)
         g.wait()
-        assert g.sort_items in (8, 12, 16)
+        assert g.sort_items in (8, 12, 16, 32)
         for i, r in ref.items():
             t = g.tree(i)
             got = [t.host_list(k, int(lev[i])) for k in (2, 4)] + [t.host_perm(0)]
