@@ -58,16 +58,14 @@ void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const ui
 void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
                  const float* xyz, uint32_t n, uint32_t* perm, float* sorted_xyz, void* leaf_key,
                  uint32_t* leaf_begin, uint64_t* status, uint32_t* tile_counter, uint32_t* n_out,
-                 hipStream_t s, const uint64_t* set_off = nullptr, uint32_t set_shift = 0);
-void launch_level(bool key64, const void* kin, const uint32_t* bin, const uint32_t* n_in,
-                  uint32_t cap_in, uint32_t n_points, void* kout, uint32_t* bout, uint32_t* cout,
-                  uint8_t* mout, uint32_t* pout, uint64_t* status, uint32_t* tile_counter,
-                  uint32_t* n_out, hipStream_t s);
+                 hipStream_t s);
 // Every level's tables in one pass over the sorted points (plain build and
 // rebuild): phase 0 counts box starts per tile and level (cnt: (L + 1) x
 // tab_tiles(n)), 1 scans them (pre, same shape; n_boxes[l] = boxes of level
 // l), 2 writes permutation, coordinates, keys, bookmarks, parents and first
-// children, 3 the child masks (mask_cap: capacity of level L - 1).
+// children, 3 the child masks (mask_cap: capacity of level L - 1). With
+// set_off (a batch), keys carry the set id from bit set_shift up and the
+// permutation is written relative to each set's first point.
 struct TabLevels {
   void* key[kMaxLevel + 1];
   uint32_t* begin[kMaxLevel + 1];
@@ -79,7 +77,8 @@ uint32_t tab_tiles(uint32_t n);
 void launch_tables(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
                    const float* xyz, uint32_t n, uint32_t L, uint32_t* cnt, uint32_t* pre,
                    const TabLevels& T, uint32_t* perm, float* sorted_xyz, uint32_t* n_boxes,
-                   uint32_t mask_cap, hipStream_t s, int phase);
+                   uint32_t mask_cap, hipStream_t s, int phase,
+                   const uint64_t* set_off = nullptr, uint32_t set_shift = 0);
 void launch_max_occupancy(const uint32_t* begin, const uint32_t* n_in, uint32_t cap,
                           uint32_t* out, hipStream_t s);
 

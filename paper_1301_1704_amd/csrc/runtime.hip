@@ -924,6 +924,22 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       for (uint32_t m = 2; m <= upto; ++m)
         for (int k = 0; k < 2; ++k) impl->lists[m].total[k] = h->list_total[k][m];
     };
+    // Every level's offsets and the small levels' entries come from one
+    // block, taken before the first list kernel, so that the host enqueues
+    // the small levels' kernels back to back (they run for microseconds
+    // each, less than an allocator call and a launch take on the host).
+    size_t lblock_b = 0;
+    for (uint32_t l = 2; l <= D; ++l) {
+      const size_t nr = nb[rs][l];
+      lblock_b += 2 * round_up((nr + 1) * 4, 256);
+      if (small_level(l)) lblock_b += round_up(27 * nr * 4, 256) + round_up(189 * nr * 4, 256);
+    }
+    char* lblock = impl->outs.get<char>(lblock_b);
+    auto carve = [&](size_t count) {
+      uint32_t* q = (uint32_t*)lblock;
+      lblock += round_up(count * 4, 256);
+      return q;
+    };
     for (uint32_t l = 2; l <= D; ++l) {
       const uint32_t nr = nb[rs][l];
       ListLevelArgs a{};
@@ -959,8 +975,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       else if (l == 2)
         P.run(K_COUNT, side + (double)nr * 8,
               [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
-      LB.off[0] = impl->outs.get<uint32_t>((size_t)nr + 1);
-      LB.off[1] = impl->outs.get<uint32_t>((size_t)nr + 1);
+      LB.off[0] = carve((size_t)nr + 1);
+      LB.off[1] = carve((size_t)nr + 1);
       {
         uint64_t* st2 = la.take_words(scan_tiles(nr));
         uint64_t* st4 = la.take_words(scan_tiles(nr));
@@ -971,8 +987,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         });
       }
       if (small_level(l)) {
-        for (int k = 0; k < 2; ++k)
-          LB.ent[k] = impl->outs.get<uint32_t>((size_t)nr * (k == 0 ? 27 : 189));
+        for (int k = 0; k < 2; ++k) LB.ent[k] = carve((size_t)nr * (k == 0 ? 27 : 189));
       } else {
         fetch_meta(meta, hm, st);  // sync point: this level's list totals
         if (hm->overflow) throw Fail{FMMDS_ERR_OVERFLOW};
@@ -1108,6 +1123,7 @@ struct BatchImpl {
   SortBufs sb{};
   uint32_t* perm = nullptr;
   float* sxyz = nullptr;
+  uint32_t* tabbuf = nullptr;  // per-tile box-start counts of every level, and their scan
   LevelBufs g[kMaxLevel + 1];
   uint64_t* fkey[kMaxLevel + 1] = {};
   uint32_t* fbegin[kMaxLevel + 1] = {};
@@ -1126,7 +1142,7 @@ struct BatchImpl {
   // zeroed per launch: dblock, histograms, digit offsets, tickets, status words
   char* ws = nullptr;
   size_t ws_b = 0, hist_at = 0, goffd_at = 0, tick_at = 0, words_at = 0;
-  size_t n_words = 0, n_tickets = 0;
+  size_t n_words = 0, n_tickets = 0, list_words = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const float* graph_xyz = nullptr;
@@ -1158,14 +1174,18 @@ void batch_sort_passes(BatchImpl& B, StatusArena& sa, Prof& P, int items) {
   }
 }
 
-void batch_front(BatchImpl& B, const float* xyz, StatusArena& sa, Prof& P) {
+void batch_front(BatchImpl& B, const float* xyz, StatusArena& sa, Prof& P, int items) {
   const hipStream_t st = B.stream;
   sa = StatusArena();
   sa.tickets = (uint32_t*)(B.ws + B.tick_at);
   sa.n_tickets = B.n_tickets;
   sa.words = (uint64_t*)(B.ws + B.words_at);
   sa.n_words = B.n_words;
-  P.run(K_ZERO, (double)B.ws_b, [&] { launch_zero(B.ws, B.ws_b, st); });
+  // only the status words this launch takes (the sort's depend on its tile
+  // size; the workspace is sized for the smallest tiles)
+  const size_t used = (size_t)B.n_pass * sort_tiles(B.P, items) * 256 + B.list_words;
+  const size_t zb = std::min(B.ws_b, round_up(B.words_at + used * 8, 256));
+  P.run(K_ZERO, (double)zb, [&] { launch_zero(B.ws, zb, st); });
   uint32_t* hist = (uint32_t*)(B.ws + B.hist_at);
   uint32_t* goffd = (uint32_t*)(B.ws + B.goffd_at);
   P.run(K_KEYGEN, (double)B.P * (12 + 8 + (B.packed ? 0 : 4)), [&] {
@@ -1179,27 +1199,33 @@ void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
   const hipStream_t st = B.stream;
   const uint32_t L = B.L;
   StatusArena sa;
-  batch_front(B, xyz, sa, P);
+  batch_front(B, xyz, sa, P, B.items);
   batch_sort_passes(B, sa, P, B.items);
   const int fin = B.n_pass & 1;
   DevMeta* meta = B.meta();
   {
-    uint64_t* stw = sa.take_words(div_up(B.P, kCompTile));
-    uint32_t* tk = sa.take_ticket();
-    P.run(K_LEAF, (double)B.P * ((B.packed ? 8 : 12) + 4 + 12 + 12), [&] {
-      launch_leaf(B.packed, true, B.sb.k[fin], B.sb.v[fin], xyz, B.P, B.perm, B.sxyz, B.g[L].key,
-                  B.g[L].begin, stw, tk, &meta->n_boxes[0][L], st, B.d_off, 3 * L);
-    });
-  }
-  for (int l = (int)L - 1; l >= 0; --l) {
-    LevelBufs& up = B.g[l];
-    LevelBufs& dn = B.g[l + 1];
-    uint64_t* stw = sa.take_words(div_up(dn.cap, kCompTile));
-    uint32_t* tk = sa.take_ticket();
-    P.run(K_LEVEL, 0.0, [&] {
-      launch_level(true, dn.key, dn.begin, &meta->n_boxes[0][l + 1], dn.cap, B.P, up.key,
-                   up.begin, up.child, up.mask, dn.parent, stw, tk, &meta->n_boxes[0][l], st);
-    });
+    // every level's tables in one pass over the sorted points (batch ranks:
+    // the composite keys make each set boundary a box boundary at every level)
+    TabLevels T{};
+    for (uint32_t l = 0; l <= L; ++l) {
+      T.key[l] = B.g[l].key;
+      T.begin[l] = B.g[l].begin;
+      T.parent[l] = B.g[l].parent;
+      T.child[l] = B.g[l].child;
+      T.mask[l] = B.g[l].mask;
+    }
+    const uint32_t tiles = tab_tiles(B.P);
+    uint32_t* tcnt = B.tabbuf;
+    uint32_t* tpre = B.tabbuf + (size_t)(L + 1) * tiles;
+    auto tab = [&](int phase) {
+      launch_tables(B.packed, true, B.sb.k[fin], B.sb.v[fin], xyz, B.P, L, tcnt, tpre, T, B.perm,
+                    B.sxyz, &meta->n_boxes[0][0], L > 0 ? B.cap[L - 1] : 0, st, phase, B.d_off,
+                    3 * L);
+    };
+    P.run(K_TCOUNT, 0.0, [&] { tab(0); });
+    P.run(K_TSCAN, 0.0, [&] { tab(1); });
+    P.run(K_LEAF, 0.0, [&] { tab(2); });
+    P.run(K_LEVEL, 0.0, [&] { tab(3); });
   }
   LevelPtrs lp{};
   for (uint32_t l = 0; l <= L; ++l) lp.begin[l] = B.g[l].begin;
@@ -1310,7 +1336,7 @@ int batch_autotune(BatchImpl& B, const float* xyz) {
     float total = 0;
     for (int rep = 0; rep < 2; ++rep) {
       StatusArena sa;
-      batch_front(B, xyz, sa, off);
+      batch_front(B, xyz, sa, off, items);
       ck(hipEventRecord(e0, B.stream));
       batch_sort_passes(B, sa, off, items);
       ck(hipEventRecord(e1, B.stream));
@@ -1397,6 +1423,7 @@ void batch_layout(BatchImpl& B, Carve& M) {
   }
   B.perm = M.get<uint32_t>(P);
   B.sxyz = M.get<float>(3 * (size_t)P);
+  B.tabbuf = M.get<uint32_t>((size_t)2 * (L + 1) * tab_tiles(P));
   uint32_t cmax = 0;
   for (uint32_t l = 0; l <= L; ++l) {
     const size_t c = B.cap[l];
@@ -1433,9 +1460,9 @@ void batch_layout(BatchImpl& B, Carve& M) {
   B.tick_at = B.goffd_at + round_up(kMaxPasses * 256 * 4, 256);
   B.n_tickets = B.n_pass + 1 + L + 2 * (L + 1);
   B.words_at = B.tick_at + round_up(B.n_tickets * 4, 256);
-  size_t words = (size_t)B.n_pass * sort_tiles(P, 8) * 256 + div_up(P, kCompTile);
-  for (uint32_t l = 0; l < L; ++l) words += div_up(B.cap[l + 1], kCompTile);
-  for (uint32_t l = 2; l <= L; ++l) words += 2 * (size_t)scan_tiles(B.cap[l]);
+  B.list_words = 0;
+  for (uint32_t l = 2; l <= L; ++l) B.list_words += 2 * (size_t)scan_tiles(B.cap[l]);
+  const size_t words = (size_t)B.n_pass * sort_tiles(P, 8) * 256 + B.list_words;
   B.n_words = words;
   B.ws_b = round_up(B.words_at + words * 8, 256);
   B.ws = M.get<char>(B.ws_b);
