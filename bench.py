@@ -84,7 +84,7 @@ KERNEL_SOURCE = {"list_fill": "lists.hip", "list_count": "lists.hip", "scan_coun
                  "near_pack": "nearfield.hip", "near_sparse": "nearfield.hip",
                  "near_dense": "nearfield.hip"}
 COUNTER_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-batch --no-serving --no-rebuild "
-                "--no-dense --no-profile --copy-calibration")
+                "--no-dense --no-nonuniform --no-profile --copy-calibration")
 
 
 def _short_name(name: str):
@@ -157,7 +157,7 @@ def counter_summary(fetch_csv: str, write_csv: str, out: str, workload_name: str
     print("\n".join(lines))
 
 
-BUILD_ONLY_FLAGS = "--no-cpu-baseline --no-batch --no-serving --no-rebuild --no-dense"
+BUILD_ONLY_FLAGS = "--no-cpu-baseline --no-batch --no-serving --no-rebuild --no-dense --no-nonuniform"
 
 
 def kernel_stats_summary(stats_csv: str, out: str, workload_name: str, flags=None):
@@ -402,6 +402,34 @@ def bench_box_types(F, torch, src, recv, kw, n_ranks=64, l_par=4):
     return res
 
 
+def bench_second_workload(F, torch, args):
+    """The sphere + clusters workload (2 x 2^24 points, max level 10, cluster
+    size 64) measured beside the default one: build rate over the same
+    number of timed steps, and its near-field sum."""
+    c = workload("nonuniform")
+    src = torch.from_numpy(c["src"]).cuda()
+    recv = torch.from_numpy(c["recv"]).cuda()
+    kw = dict(max_level=c["max_level"], key_bits=c["key_bits"], cluster_s=c["cluster_s"])
+    for _ in range(args.warmup):
+        F.build(src, recv, **kw).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F.build(src, recv, **kw).free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    t = F.build(src, recv, **kw)
+    torch.cuda.synchronize()
+    depth = t.depth
+    t.free()
+    res = {"workload": c["name"], "value": (src.shape[0] + recv.shape[0]) / dt,
+           "unit": "points/s", "ms_per_step": dt * 1e3, "steps": args.steps, "depth": depth}
+    log(f"{c['name']}: {dt * 1e3:.3f} ms per build, {res['value']:.3g} points/s")
+    if not args.no_near_field:
+        res["near_field"] = bench_near_field(F, torch, src, recv, kw)
+    return res
+
+
 def bench_near_field(F, torch, src, recv, kw, reps=5):
     """Near-field Laplace sum over the E2 lists of the benchmark build (one
     charge per source point): pairs per second and FP32 rate, 9 flops per
@@ -623,6 +651,8 @@ def main():
                     help="skip the incremental rebuild measurement")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-histogram variant measurement")
+    ap.add_argument("--no-nonuniform", action="store_true",
+                    help="skip the sphere + clusters workload measured beside the uniform one")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -772,6 +802,8 @@ def main():
         line["rebuild"] = bench_rebuild(F, torch, c, kw)
     if not args.no_dense and c["max_level"] <= 8:
         line["dense"] = bench_dense(F, torch, src, recv, kw)
+    if not args.no_nonuniform and args.workload == "uniform":
+        line["nonuniform"] = bench_second_workload(F, torch, args)
     if not args.no_batch:
         line["batched"] = bench_batched(F, torch, args, batch_sets)
         if cpu_batch is not None:

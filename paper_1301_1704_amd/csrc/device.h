@@ -137,6 +137,28 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* col, uint64_t stride, uin
   return excl;
 }
 
+// The same look-back for a tile that has already published its aggregate
+// (kStAgg | agg at its own slot): walk back, then publish the inclusive sum.
+__device__ __forceinline__ uint64_t lookback_published(uint64_t* col, uint64_t stride,
+                                                       uint32_t tile, uint64_t agg) {
+  if (tile == 0) return 0;  // tile 0 published its inclusive value already
+  uint64_t excl = 0;
+  int64_t t = (int64_t)tile - 1;
+  while (true) {
+    const uint64_t s = ld_status(col + (uint64_t)t * stride);
+    const uint64_t f = s >> 62;
+    if (f == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & kStVal;
+    if (f == 2) break;
+    --t;
+  }
+  st_status(col + (uint64_t)tile * stride, kStInc | (excl + agg));
+  return excl;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

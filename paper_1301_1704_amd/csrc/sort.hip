@@ -127,10 +127,11 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 // input order. The tile's 256 digit counts are then chained across tiles by
 // decoupled look-back (thread d < 256 owns digit d), the tile is staged in
 // LDS in digit order, and written out so that consecutive threads store
-// consecutive addresses of one digit's run. Tiles of 8192 packed elements
-// (512 threads) halve the chain of look-backs of 4096-element tiles, which
-// is what sets the pass's length: without its look-back a 4096-element pass
-// over 2^24 elements takes ~75 us instead of ~125 us.
+// consecutive addresses of one digit's run. The look-back chain is what sets
+// the pass's length (without it a 4096-element pass over 2^24 elements takes
+// ~75 us instead of ~125 us), so each tile publishes its digit counts (LDS
+// atomics) before it ranks, and tiles of 8192 packed elements (512 threads)
+// halve the chain of 4096-element tiles.
 // ---------------------------------------------------------------------------
 template <bool PACKED, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   __shared__ uint64_t s_key[TILE];
   __shared__ uint32_t s_val[PACKED ? 1 : TILE];
   __shared__ uint32_t s_hist[W][256];
+  __shared__ uint32_t s_cnt[256];  // the tile's digit counts, published before the ranking
   __shared__ uint32_t s_lstart[256];
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_scan[4];
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   for (uint32_t i = tid; i < W * 256; i += BLOCK) (&s_hist[0][0])[i] = 0;
+  if (tid < 256) s_cnt[tid] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
   // With the count on the device the grid covers the capacity; tiles past
@@ -169,6 +172,16 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     const uint64_t e = wbase + (uint64_t)i * 64 + lane;
     k[i] = e < n ? kin[e] : 0;
     if (!PACKED) v[i] = e < n ? vin[e] : 0;
+  }
+  // The tile's digit counts first (LDS atomics), published at once, so that
+  // later tiles' look-backs find them while this tile still ranks.
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (wbase + (uint64_t)i * 64 + lane < n) atomicAdd(&s_cnt[(uint32_t)(k[i] >> shift) & 0xFFu], 1u);
+  __syncthreads();
+  if (tid < 256) {
+    const uint64_t agg = s_cnt[tid];
+    st_status(status + (uint64_t)tile * 256 + tid, (tile == 0 ? kStInc : kStAgg) | agg);
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
     const uint32_t lstart = wpre + inc - cnt;
     s_lstart[d] = lstart;
-    const uint64_t excl = lookback(status + d, 256, tile, cnt);
+    const uint64_t excl = lookback_published(status + d, 256, tile, cnt);
     s_base[d] = goff[d] + (uint32_t)excl - lstart;
   }
   __syncthreads();
