@@ -45,8 +45,14 @@ struct SortBufs {
 
 // ---- sort.hip
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// Keys and the sort elements (key, index) of n points, and per block of the
+// launch (keygen_blocks(n) of them) one row of n_pass x 256 digit counts.
+uint32_t keygen_blocks(uint32_t n);
 void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
-                   uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err, hipStream_t s);
+                   uint32_t* vals, uint32_t n_pass, uint32_t* rows, uint32_t* err, hipStream_t s);
+// Those rows added into the pass histograms hist (zeroed, n_pass x 256).
+void launch_reduce_rows(const uint32_t* rows, uint32_t n_rows, uint32_t* hist, uint32_t n_pass,
+                        hipStream_t s);
 void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass, hipStream_t s);
 uint32_t sort_tiles(uint32_t n, int items);
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,

@@ -648,6 +648,10 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         }
       }
     }
+    // keygen's per-block digit-count rows, per set
+    uint32_t* krows[2] = {nullptr, nullptr};
+    for (int s = 0; s < nsets; ++s)
+      krows[s] = temps.get<uint32_t>((size_t)keygen_blocks(sets[s].n) * n_pass * 256);
     // every level's tables in one pass (not the dense variant): per set the
     // per-tile box-start counts of every level and their scan
     uint32_t* tabbuf[2] = {nullptr, nullptr};
@@ -685,10 +689,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       uint32_t* h = hist + s * kMaxPasses * 256;
       uint32_t* g = goff + s * kMaxPasses * 256;
       P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
-        launch_keygen(sets[s].xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range,
-                      st);
+        launch_keygen(sets[s].xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, krows[s],
+                      &meta->err_range, st);
       });
-      P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+      P.run(K_DIGITS, (double)keygen_blocks(n) * n_pass * 1024, [&] {
+        launch_reduce_rows(krows[s], keygen_blocks(n), h, n_pass, st);
+        launch_digit_offsets(h, g, n_pass, st);
+      });
     }
 
     for (int s = 0; s < nsets; ++s) {
@@ -774,10 +781,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         }
         if (!plain) {  // (plain builds enqueued these above)
           P.run(K_KEYGEN, (double)n * (packed ? 12 + 8 : 12 + 8 + 4), [&] {
-            launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range,
-                          st);
+            launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, krows[s],
+                          &meta->err_range, st);
           });
-          P.run(K_DIGITS, (double)n_pass * 2048, [&] { launch_digit_offsets(h, g, n_pass, st); });
+          P.run(K_DIGITS, (double)keygen_blocks(n) * n_pass * 1024, [&] {
+            launch_reduce_rows(krows[s], keygen_blocks(n), h, n_pass, st);
+            launch_digit_offsets(h, g, n_pass, st);
+          });
         }
         for (uint32_t p = 0; p < n_pass; ++p) {
           const int a = p & 1, b = a ^ 1;
@@ -875,9 +885,13 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       uint32_t* h = hist + s * kMaxPasses * 256;
       uint32_t* g = goff + s * kMaxPasses * 256;
       P.run(K_KEYGEN, 0.0, [&] {
-        launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, h, &meta->err_range, st);
+        launch_keygen(S.xyz, n, L, packed, sb.k[0], sb.v[0], n_pass, krows[s], &meta->err_range,
+                      st);
       });
-      P.run(K_DIGITS, 0.0, [&] { launch_digit_offsets(h, g, n_pass, st); });
+      P.run(K_DIGITS, 0.0, [&] {
+        launch_reduce_rows(krows[s], keygen_blocks(n), h, n_pass, st);
+        launch_digit_offsets(h, g, n_pass, st);
+      });
       for (uint32_t p = 0; p < n_pass; ++p) {
         const int a = p & 1, b = a ^ 1;
         uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);

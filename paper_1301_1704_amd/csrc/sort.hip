@@ -42,15 +42,19 @@ struct P3 {
 
 // Each thread loads kKeyItems points (one 64-point run per wave and item,
 // all issued before any is used), so the loads of a block are in flight
-// together rather than one per loop trip.
+// together rather than one per loop trip. Each block writes its digit
+// histograms as one row (no atomics: thousands of blocks adding into the same
+// 256 bins per pass serialize on those addresses); the digit-offset kernel
+// adds the rows.
 constexpr int kKeyItems = 8;
 constexpr int kKeyChunk = 256 * kKeyItems;
+constexpr uint32_t kKeyMaxBlocks = 4096;
 
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint32_t n, uint32_t L,
                                                 uint64_t* __restrict__ keys,
                                                 uint32_t* __restrict__ vals, uint32_t n_pass,
-                                                uint32_t* __restrict__ hist,
+                                                uint32_t* __restrict__ rows,
                                                 uint32_t* __restrict__ err) {
   __shared__ uint32_t s_hist[kMaxPasses * 256];
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
@@ -83,20 +87,44 @@ __global__ __launch_bounds__(256) void k_keygen(const P3* __restrict__ xyz, uint
   }
   if (bad) atomicOr(err, 1u);
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256)
-    if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+  uint32_t* row = rows + (uint64_t)blockIdx.x * n_pass * 256;
+  for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) row[i] = s_hist[i];
+}
+
+uint32_t keygen_blocks(uint32_t n) {
+  return std::max<uint32_t>(1, std::min<uint32_t>(div_up(n, kKeyChunk), kKeyMaxBlocks));
 }
 
 void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64_t* keys,
-                   uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
+                   uint32_t* vals, uint32_t n_pass, uint32_t* rows, uint32_t* err,
                    hipStream_t s) {
-  const uint32_t grid = std::min<uint32_t>(div_up(n, kKeyChunk), 2048);
+  const uint32_t grid = keygen_blocks(n);
   if (packed)
     hipLaunchKernelGGL(k_keygen<true>, dim3(grid), dim3(256), 0, s, (const P3*)xyz, n, L, keys,
-                       vals, n_pass, hist, err);
+                       vals, n_pass, rows, err);
   else
     hipLaunchKernelGGL(k_keygen<false>, dim3(grid), dim3(256), 0, s, (const P3*)xyz, n, L, keys,
-                       vals, n_pass, hist, err);
+                       vals, n_pass, rows, err);
+}
+
+// Keygen's per-block rows added into the zeroed pass histograms: block
+// (b, p) adds rows b, b + gridDim.x, ... of pass p, then one atomic per bin
+// (a few dozen per address instead of one per keygen block).
+constexpr uint32_t kRowReduceBlocks = 64;
+__global__ __launch_bounds__(256) void k_reduce_rows(const uint32_t* __restrict__ rows,
+                                                     uint32_t n_rows, uint32_t n_pass,
+                                                     uint32_t* __restrict__ hist) {
+  const uint32_t p = blockIdx.y, d = threadIdx.x;
+  uint32_t c = 0;
+  for (uint32_t r = blockIdx.x; r < n_rows; r += gridDim.x)
+    c += rows[((uint64_t)r * n_pass + p) * 256 + d];
+  if (c) atomicAdd(&hist[p * 256 + d], c);
+}
+
+void launch_reduce_rows(const uint32_t* rows, uint32_t n_rows, uint32_t* hist, uint32_t n_pass,
+                        hipStream_t s) {
+  const dim3 grid(std::min(kRowReduceBlocks, n_rows), n_pass);
+  hipLaunchKernelGGL(k_reduce_rows, grid, dim3(256), 0, s, rows, n_rows, n_pass, hist);
 }
 
 // Exclusive scan of each pass's 256-bin histogram: where digit d starts.
