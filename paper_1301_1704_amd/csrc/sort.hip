@@ -161,6 +161,14 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 // atomics) before it ranks, and tiles of 8192 packed elements (512 threads)
 // halve the chain of 4096-element tiles.
 // ---------------------------------------------------------------------------
+// The 8-bit digit at `shift`. A packed element holds the key in its high
+// word, and its passes start at shift 32.
+template <bool PACKED>
+__device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t shift) {
+  return PACKED ? __builtin_amdgcn_ubfe((uint32_t)(k >> 32), shift - 32u, 8u)
+                : (uint32_t)(k >> shift) & 0xFFu;
+}
+
 template <bool PACKED, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
@@ -191,21 +199,26 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   // the count exit (tiles only look back at lower tile ids).
   if ((uint64_t)tile * TILE >= n && tile > 0) return;
   const uint64_t wbase = (uint64_t)tile * TILE + (uint64_t)w * WSEG;
+  // Item i of this lane is element wbase + 64 i + lane, valid while
+  // 64 i + lane < lim (32-bit tests; the wave's base pointer is uniform).
+  const uint32_t lim = (uint32_t)min((uint64_t)WSEG, n > wbase ? (uint64_t)n - wbase : 0ull);
+  const uint64_t* __restrict__ kw = kin + wbase;
+  const uint32_t* __restrict__ vw = PACKED ? nullptr : vin + wbase;
 
   uint64_t k[ITEMS];
   uint32_t v[ITEMS];
   uint32_t r[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint64_t e = wbase + (uint64_t)i * 64 + lane;
-    k[i] = e < n ? kin[e] : 0;
-    if (!PACKED) v[i] = e < n ? vin[e] : 0;
+    const uint32_t j = 64u * i + lane;
+    k[i] = j < lim ? kw[j] : 0;
+    if (!PACKED) v[i] = j < lim ? vw[j] : 0;
   }
   // The tile's digit counts first (LDS atomics), published at once, so that
   // later tiles' look-backs find them while this tile still ranks.
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i)
-    if (wbase + (uint64_t)i * 64 + lane < n) atomicAdd(&s_cnt[(uint32_t)(k[i] >> shift) & 0xFFu], 1u);
+    if (64u * i + lane < lim) atomicAdd(&s_cnt[sort_digit<PACKED>(k[i], shift)], 1u);
   __syncthreads();
   if (tid < 256) {
     const uint64_t agg = s_cnt[tid];
@@ -213,20 +226,26 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const bool valid = wbase + (uint64_t)i * 64 + lane < n;
-    const uint32_t d = (uint32_t)(k[i] >> shift) & 0xFFu;
-    uint64_t peers = __ballot(valid);
+    const bool valid = 64u * i + lane < lim;
+    const uint32_t d = sort_digit<PACKED>(k[i], shift);
+    // peers: the valid lanes whose digit equals this lane's. Per bit b, m is
+    // all ones where this lane's bit is 0, so that (ballot ^ m) keeps the
+    // lanes that agree with it on bit b (one three-input bit op per half).
+    const uint64_t vb = __ballot(valid);
+    uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
+    const uint32_t nd = ~d;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
+      const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)nd, b, 1);
+      const uint64_t bal = __ballot(m == 0u);
+      plo &= (uint32_t)bal ^ m;
+      phi &= (uint32_t)(bal >> 32) ^ m;
     }
-    const uint32_t below = mbcnt(peers);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
     uint32_t prev = 0;
     if (valid) prev = s_hist[w][d];
     r[i] = prev + below;
-    if (valid && below == 0) s_hist[w][d] = prev + (uint32_t)__popcll(peers);
+    if (valid && below == 0) s_hist[w][d] = prev + (uint32_t)(__popc(plo) + __popc(phi));
   }
   __syncthreads();
 
@@ -259,8 +278,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
 
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    if (wbase + (uint64_t)i * 64 + lane < n) {
-      const uint32_t dd = (uint32_t)(k[i] >> shift) & 0xFFu;
+    if (64u * i + lane < lim) {
+      const uint32_t dd = sort_digit<PACKED>(k[i], shift);
       const uint32_t lp = s_lstart[dd] + s_hist[w][dd] + r[i];
       s_key[lp] = k[i];
       if (!PACKED) s_val[lp] = v[i];
@@ -271,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   const uint32_t tcount = (uint32_t)min((uint64_t)TILE, (uint64_t)n - tbase);
   for (uint32_t j = tid; j < tcount; j += BLOCK) {
     const uint64_t kk = s_key[j];
-    const uint32_t dd = (uint32_t)(kk >> shift) & 0xFFu;
+    const uint32_t dd = sort_digit<PACKED>(kk, shift);
     const uint32_t g = s_base[dd] + j;
     kout[g] = kk;
     if (!PACKED) vout[g] = s_val[j];
