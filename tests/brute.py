@@ -9,7 +9,8 @@ than the oracle takes:
     first, rather than by interleaving the bits of the finest coordinates;
   - lists come from enumerating every (receiver box, source box) pair and
     testing the distance conditions on coordinates (Section 1.4 E2, E4).
-Only for inputs of a few hundred points.
+Only for inputs of a few hundred points. At the end: the list totals of a
+slab of box centres in closed form, for sizes no enumeration reaches.
 """
 from __future__ import annotations
 
@@ -211,3 +212,28 @@ def near_field(src, recv, depth: int, charges=None):
             f += (1.0 if charges is None else float(charges[i])) / r
         out.append(f)
     return np.asarray(out)
+
+
+def slab_points(level: int, m: int) -> np.ndarray:
+    """One point at the centre of every level-``level`` box whose z-coordinate
+    is below m (the slab 2^level x 2^level x m), x fastest."""
+    side = 1 << level
+    ax = ((np.arange(side, dtype=np.float64) + 0.5) / side).astype(np.float32)
+    z, y, x = np.meshgrid(ax[:m], ax, ax, indexing="ij")
+    return np.ascontiguousarray(np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1))
+
+
+def slab_list_totals(level: int, m: int):
+    """E2 / E4 totals at ``level`` of slab_points(level, m) (m even, every
+    box of the slab nonempty, sources = receivers), from Section 1.4's
+    definitions. Both lists are products over the axes: a box at coordinate
+    c has b(c) axis neighbours within one box (3, 2 at an end of the axis)
+    and a(c) children of its parent's axis neighbours (6, 4 when the parent is
+    at an end). A full axis of 2^level boxes gives sum b = 3 * 2^level - 2 and
+    sum a = 6 * 2^level - 8; the z axis, m boxes from 0 with m / 2 parents,
+    sum b = 3m - 2 and sum a = 6m - 8. So E2 = prod sum b and
+    E4 = prod sum a - E2 (m = 2^level gives the full-grid closed forms)."""
+    bx, ax = 3 * (1 << level) - 2, 6 * (1 << level) - 8
+    bz, az = 3 * m - 2, 6 * m - 8
+    e2 = bx * bx * bz
+    return e2, ax * ax * az - e2

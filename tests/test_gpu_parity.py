@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+import brute
 import parity
 from paper_1301_1704_amd import inputs as I
 
@@ -191,6 +192,35 @@ def test_list_level_errors(F):
         with pytest.raises(F.FmmdsError) as e:
             t.neighbors(bad)
         assert e.value.status == F.ERR_LEVEL
+    t.free()
+
+
+@pytest.mark.timeout(300)
+def test_list_overflow_error(F):
+    """A level whose E4 list needs 2^32 or more entries fails with
+    ERR_OVERFLOW (32-bit CSR offsets), and the library stays usable: the same
+    33.5M points one level shallower build, with list totals equal to the
+    closed form."""
+    import torch
+    L, m = 9, 128
+    side = 1 << L
+    pts = brute.slab_points(L, m)
+    e2_9, e4_9 = brute.slab_list_totals(L, m)
+    assert e2_9 < 2**32 <= e4_9  # 6.24e9 E4 entries at level 9
+    g = parity.to_gpu(pts)
+    del pts
+    print(f"slab {side}x{side}x{m} at level {L}: expecting ERR_OVERFLOW", flush=True)
+    with pytest.raises(F.FmmdsError) as e:
+        F.build(g, None, max_level=L, key_bits=64)
+    assert e.value.status == F.ERR_OVERFLOW
+    torch.cuda.synchronize()
+    t = F.build(g, None, max_level=L - 1, key_bits=64)
+    torch.cuda.synchronize()
+    e2_8, e4_8 = brute.slab_list_totals(L - 1, m // 2)
+    assert e4_8 < 2**32
+    assert t.n_boxes(0, L - 1) == (side // 2) ** 2 * (m // 2)
+    assert t.neighbors(L - 1)[3] == e2_8
+    assert t.interactions(L - 1)[3] == e4_8
     t.free()
 
 

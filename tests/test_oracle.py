@@ -180,6 +180,23 @@ def test_depth_rule_by_brute_force(oracle_lib, s):
 
 # ------------------------------------------------------------ closed forms
 
+@pytest.mark.parametrize("L,m", [(3, 2), (4, 6), (5, 8), (5, 32)])
+def test_slab_closed_forms(oracle_lib, L, m):
+    """The oracle's finest-level list totals on a slab of box centres equal
+    the slab closed form (which reduces to the full-grid one at m = 2^L)."""
+    e2, e4 = brute.slab_list_totals(L, m)
+    t = oracle_lib.OracleTree(brute.slab_points(L, m), key_bits=64, max_level=L)
+    assert t.n_boxes(0, L) == (1 << L) ** 2 * m
+    o2, _ = t.list(2, L)
+    o4, _ = t.list(4, L)
+    assert (int(o2[-1]), int(o4[-1])) == (e2, e4)
+
+
+def test_slab_closed_form_is_the_full_grid_one():
+    for L, e2, e4 in golden_io.read_table("closed_forms.txt"):
+        assert brute.slab_list_totals(L, 1 << L) == (e2, e4)
+
+
 @pytest.mark.parametrize("row", golden_io.read_table("closed_forms.txt")[:5])
 def test_full_grid_closed_forms(oracle_lib, row):
     L, e2_total, e4_total = row
