@@ -501,7 +501,9 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     for (int s = 0; s < nsets; ++s) {
       const uint32_t n = sets[s].n;
       const uint32_t np = inc[s] ? inc_pass[s] : n_pass;
-      words += (size_t)np * sort_tiles(n, kSortItemsDefault) * 256 + 2 * div_up(n, kCompTile);
+      // status words of each sort pass, for the tile size that pass runs with
+      const int items = (packed && !dense && !inc[s]) ? kSortWide : kSortItemsDefault;
+      words += (size_t)np * sort_tiles(n, items) * 256 + 2 * div_up(n, kCompTile);
       tickets += np + 2 + L;
       if (dense) {
         for (uint32_t l = 0; l <= L; ++l) words += dense_scan_tiles(1u << (3 * l));
@@ -792,7 +794,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         for (uint32_t p = 0; p < n_pass; ++p) {
           const int a = p & 1, b = a ^ 1;
           const uint32_t shift = (packed ? 32 : 0) + 8 * p;
-          uint64_t* stw = sa.take_words((size_t)sort_tiles(n, kSortItemsDefault) * 256);
+          uint64_t* stw =
+              sa.take_words((size_t)sort_tiles(n, packed ? kSortWide : kSortItemsDefault) * 256);
           uint32_t* tk = sa.take_ticket();
           P.run(K_SORT, (double)n * (packed ? 16 : 24), [&] {
             launch_sort_pass(packed, sb.k[a], sb.k[b], sb.v[a], sb.v[b], n, shift, g + p * 256,

@@ -114,10 +114,17 @@ constexpr uint32_t kRowReduceBlocks = 64;
 __global__ __launch_bounds__(256) void k_reduce_rows(const uint32_t* __restrict__ rows,
                                                      uint32_t n_rows, uint32_t n_pass,
                                                      uint32_t* __restrict__ hist) {
-  const uint32_t p = blockIdx.y, d = threadIdx.x;
-  uint32_t c = 0;
-  for (uint32_t r = blockIdx.x; r < n_rows; r += gridDim.x)
-    c += rows[((uint64_t)r * n_pass + p) * 256 + d];
+  const uint32_t p = blockIdx.y, d = threadIdx.x, G = gridDim.x;
+  uint32_t c = 0, r = blockIdx.x;
+  // eight rows' loads in flight per round
+  for (; r + 7 * G < n_rows; r += 8 * G) {
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) v[t] = rows[((uint64_t)(r + t * G) * n_pass + p) * 256 + d];
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) c += v[t];
+  }
+  for (; r < n_rows; r += G) c += rows[((uint64_t)r * n_pass + p) * 256 + d];
   if (c) atomicAdd(&hist[p * 256 + d], c);
 }
 
