@@ -137,23 +137,41 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* col, uint64_t stride, uin
   return excl;
 }
 
-// The same look-back for a tile that has already published its aggregate
-// (kStAgg | agg at its own slot): walk back, then publish the inclusive sum.
-__device__ __forceinline__ uint64_t lookback_published(uint64_t* col, uint64_t stride,
-                                                       uint32_t tile, uint64_t agg) {
+// A tile whose column holds its aggregate already (published before the
+// tile's other work, tile 0 publishing its inclusive value): the walk back to
+// the nearest inclusive prefix, W predecessors' status words loaded at once
+// per round and summed in order up to the first inclusive prefix; an
+// unpublished word ends the round, and the next round starts there. Then the
+// tile's inclusive value is published; returns the exclusive prefix.
+template <int W>
+__device__ __forceinline__ uint64_t lookback_window(uint64_t* col, uint64_t stride, uint32_t tile,
+                                                    uint64_t agg) {
   if (tile == 0) return 0;  // tile 0 published its inclusive value already
   uint64_t excl = 0;
   int64_t t = (int64_t)tile - 1;
   while (true) {
-    const uint64_t s = ld_status(col + (uint64_t)t * stride);
-    const uint64_t f = s >> 62;
-    if (f == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
+    uint64_t s[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i)  // below tile 0 nothing is read: tile 0 ends every walk
+      s[i] = t - i >= 0 ? ld_status(col + (uint64_t)(t - i) * stride) : kStInc;
+    bool stop = false, found = false;
+    uint32_t used = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (!stop) {
+        const uint64_t f = s[i] >> 62;
+        if (f == 0) {
+          stop = true;
+        } else {
+          excl += s[i] & kStVal;
+          ++used;
+          if (f == 2) stop = found = true;
+        }
+      }
     }
-    excl += s & kStVal;
-    if (f == 2) break;
-    --t;
+    if (found) break;
+    t -= used;
+    if (used < (uint32_t)W) __builtin_amdgcn_s_sleep(1);
   }
   st_status(col + (uint64_t)tile * stride, kStInc | (excl + agg));
   return excl;

@@ -165,8 +165,9 @@ void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass,
 // consecutive addresses of one digit's run. The look-back chain is what sets
 // the pass's length (without it a 4096-element pass over 2^24 elements takes
 // ~75 us instead of ~125 us), so each tile publishes its digit counts (LDS
-// atomics) before it ranks, and tiles of 8192 packed elements (512 threads)
-// halve the chain of 4096-element tiles.
+// atomics) before it ranks, tiles of 8192 packed elements (512 threads)
+// halve the chain of 4096-element tiles, and each digit's walk loads four
+// predecessors' words at a time.
 // ---------------------------------------------------------------------------
 // The 8-bit digit at `shift`. A packed element holds the key in its high
 // word, and its passes start at shift 32.
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
     const uint32_t lstart = wpre + inc - cnt;
     s_lstart[d] = lstart;
-    const uint64_t excl = lookback_published(status + d, 256, tile, cnt);
+    const uint64_t excl = lookback_window<4>(status + d, 256, tile, cnt);
     s_base[d] = goff[d] + (uint32_t)excl - lstart;
   }
   __syncthreads();
