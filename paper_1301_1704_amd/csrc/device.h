@@ -111,32 +111,6 @@ __device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish `agg` for `tile` in the status column starting at `col` with
-// `stride` words between consecutive tiles; return the exclusive prefix.
-__device__ __forceinline__ uint64_t lookback(uint64_t* col, uint64_t stride, uint32_t tile,
-                                             uint64_t agg) {
-  if (tile == 0) {
-    st_status(col, kStInc | agg);
-    return 0;
-  }
-  st_status(col + (uint64_t)tile * stride, kStAgg | agg);
-  uint64_t excl = 0;
-  int64_t t = (int64_t)tile - 1;
-  while (true) {
-    const uint64_t s = ld_status(col + (uint64_t)t * stride);
-    const uint64_t f = s >> 62;
-    if (f == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += s & kStVal;
-    if (f == 2) break;
-    --t;
-  }
-  st_status(col + (uint64_t)tile * stride, kStInc | (excl + agg));
-  return excl;
-}
-
 // A tile whose column holds its aggregate already (published before the
 // tile's other work, tile 0 publishing its inclusive value): the walk back to
 // the nearest inclusive prefix, W predecessors' status words loaded at once
