@@ -72,6 +72,41 @@ def test_uniform_separate_ragged(F, oracle_lib, n_src, n_recv, L):
     _run(F, oracle_lib, src, recv, L=L)[0].free()
 
 
+def _sweep_case(i: int):
+    """Configuration i of the seeded sweep: sizes log-uniform in [1, 2^17]
+    around tile edges, uniform / clustered / sphere + clusters points, shared
+    or separate sets, 32- or 64-bit keys, fixed depth or the cluster-size
+    rule. Drawn from the project's splitmix64 stream, so the cases are fixed."""
+    u = I.uniform53(I.stream_seed(9100, i), 12)
+    def size(x):
+        n = int(2.0 ** (17 * x))
+        return max(1, n + (int(u[11] * 7) - 3 if n > 8 else 0))  # a few off the power of two
+    n_src = size(u[0])
+    n_recv = None if u[1] < 0.3 else size(u[2])
+    kind = int(u[3] * 3)
+    def pts(seed, n):
+        if kind == 0:
+            return I.uniform_points(seed, n)
+        if kind == 1:
+            return I.cluster_points(seed, n, I.cluster_centres(seed + 1, 8), 0.02)
+        return I.sphere_cluster_points(seed, 9101, n)
+    src = pts(9200 + i, n_src)
+    recv = None if n_recv is None else pts(9300 + i, n_recv)
+    n_max = max(n_src, n_recv or 0)
+    L = 2 + int(u[4] * (min(8, I.level_for_size(n_max, 1) + 1) - 1))  # 2 .. 8, deeper for more points
+    kb = 32 if (u[5] < 0.4 and 3 * L <= 32) else 64
+    s = 0 if u[6] < 0.5 else (16 if u[7] < 0.5 else 64)
+    return src, recv, L, kb, s
+
+
+@pytest.mark.parametrize("i", range(24))
+def test_seeded_sweep(F, oracle_lib, i):
+    """Twenty-four fixed random configurations, whole output against the
+    oracle."""
+    src, recv, L, kb, s = _sweep_case(i)
+    _run(F, oracle_lib, src, recv, L=L, kb=kb, s=s)[0].free()
+
+
 @pytest.mark.parametrize("kb", [32, 64])
 def test_nonuniform_depth_rule(F, oracle_lib, kb):
     """Sphere + clusters with the cluster-size depth rule."""
