@@ -54,16 +54,21 @@ __device__ __forceinline__ float pair_term(const float4 x, float yx, float yy, f
   return r2 > 0.0f ? x.w * rsqrtf(r2) : 0.0f;
 }
 
-// Sparse path: one thread per receiver box, up to kNearRecv of its points at
-// a time: each source point is loaded once for all of them. The list is
+// Sparse path: one thread per receiver box, up to R of its points at a time:
+// each source point is loaded once for all of them. R = 4 suits boxes of one
+// or two points (uniform input); with more points per box (sphere, clusters)
+// a wave then walks its lists twice whenever one of its boxes has five or
+// more, so R = 8 is taken when the receivers average more than two points
+// per finest box (measured: 2.24 against 2.86 ms on the uniform benchmark
+// build, 4.36 against 3.83 ms on sphere + clusters). The list is
 // walked eight entries at a time (their source ranks, then their bookmarks,
 // then their points), so that the dependent loads of eight entries overlap.
 // Every receiver's terms are added in list order, point by point. A box of
 // more than kNearDenseMin points is not summed here: its thread appends the
 // box's tasks (box, chunk of 64 receivers) to the dense path's task list.
 constexpr uint32_t kNearBatch = 8;
-constexpr uint32_t kNearRecv = 4;
 
+template <uint32_t R>
 __global__ __launch_bounds__(256) void k_near_field(
     uint32_t n_rbox, const uint32_t* __restrict__ rbegin, const float* __restrict__ rxyz,
     const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ e2_off,
@@ -80,10 +85,10 @@ __global__ __launch_bounds__(256) void k_near_field(
       my_tasks = (k1 - k0 + 63u) / 64u;
     } else {
       const uint32_t e0 = e2_off[b], e1 = e2_off[b + 1];
-      for (uint32_t kc = k0; kc < k1; kc += kNearRecv) {
-        float yx[kNearRecv], yy[kNearRecv], yz[kNearRecv], acc[kNearRecv];
+      for (uint32_t kc = k0; kc < k1; kc += R) {
+        float yx[R], yy[R], yz[R], acc[R];
 #pragma unroll
-        for (uint32_t r = 0; r < kNearRecv; ++r) {
+        for (uint32_t r = 0; r < R; ++r) {
           const uint32_t k = min(kc + r, k1 - 1);  // extra lanes repeat the last point
           yx[r] = rxyz[3 * (uint64_t)k], yy[r] = rxyz[3 * (uint64_t)k + 1],
           yz[r] = rxyz[3 * (uint64_t)k + 2];
@@ -105,14 +110,14 @@ __global__ __launch_bounds__(256) void k_near_field(
             for (uint32_t i = i0[j]; i < i1[j]; ++i) {
               const float4 x = src[i];
 #pragma unroll
-              for (uint32_t r = 0; r < kNearRecv; ++r) acc[r] += pair_term(x, yx[r], yy[r], yz[r]);
+              for (uint32_t r = 0; r < R; ++r) acc[r] += pair_term(x, yx[r], yy[r], yz[r]);
             }
             pts += i1[j] - i0[j];
           }
         }
-        const uint32_t nr = min(kNearRecv, k1 - kc);
+        const uint32_t nr = min(R, k1 - kc);
 #pragma unroll
-        for (uint32_t r = 0; r < kNearRecv; ++r)
+        for (uint32_t r = 0; r < R; ++r)
           if (r < nr) phi[rperm[kc + r]] = acc[r];
         pairs += (uint64_t)pts * nr;
       }
@@ -251,8 +256,14 @@ void launch_near_field(uint32_t n_rbox, uint32_t n_recv, const uint32_t* rbegin,
                        float* phi, unsigned long long* n_pairs, uint2* tasks,
                        uint32_t* counters, hipStream_t s) {
   if (n_rbox == 0) return;
-  hipLaunchKernelGGL(k_near_field, dim3(div_up(n_rbox, 256)), dim3(256), 0, s, n_rbox, rbegin,
-                     rxyz, rperm, e2_off, e2_ent, sbegin, src, phi, n_pairs, tasks, counters);
+  if (n_recv > 2ull * n_rbox)
+    hipLaunchKernelGGL(k_near_field<8>, dim3(div_up(n_rbox, 256)), dim3(256), 0, s, n_rbox,
+                       rbegin, rxyz, rperm, e2_off, e2_ent, sbegin, src, phi, n_pairs, tasks,
+                       counters);
+  else
+    hipLaunchKernelGGL(k_near_field<4>, dim3(div_up(n_rbox, 256)), dim3(256), 0, s, n_rbox,
+                       rbegin, rxyz, rperm, e2_off, e2_ent, sbegin, src, phi, n_pairs, tasks,
+                       counters);
   // Persistent waves over the dense tasks: enough for the most tasks the
   // receivers can make, at most eight blocks per compute unit; they exit
   // when the ticket passes the task count.
