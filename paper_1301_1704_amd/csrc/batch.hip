@@ -4,8 +4,11 @@
 // Every point carries a composite key: its set id above 3 * L_all bits, and
 // below them the Morton index of its box at the set's own level L_i shifted
 // left by 3 * (L_all - L_i), where L_all is the deepest level of the batch.
-// One sort then orders all sets at once (set first, then box, then index),
-// and shifting the composite key right by 3 * (L_all - l) yields, for every set
+// The points of a batch arrive grouped by set, in set order, so the sort
+// orders each set within its own range on the Morton bits alone (sort tiles
+// never straddle two sets, and each set has its own digit offsets); the
+// result is the order of the composite keys (set, then box, then index).
+// Shifting a composite key right by 3 * (L_all - l) yields, for every set
 // with L_i >= l, its level-l Morton index (Section 1.4) with the set id above
 // bit 3l. The compaction and hierarchy kernels of the single build then run
 // unchanged over the whole batch; the kernels here find where each set starts
@@ -19,43 +22,28 @@ struct P3b {
   float x, y, z;
 };
 
-// The set a point belongs to: the last i with set_off[i] <= e.
-__device__ __forceinline__ uint32_t find_set(const uint64_t* __restrict__ off, uint32_t n_sets,
-                                             uint64_t e) {
-  uint32_t lo = 0, hi = n_sets;  // off[lo] <= e < off[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= e) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Each block takes one contiguous range of `chunk` points: it finds the set
-// of its first point once, and each thread then moves forward through the
-// sets (which hold at least one point each) as its points advance. About
-// 2048 blocks, so that the digit histograms are merged by few atomics.
-
+// One block per keygen tile: at most 8192 points, all of one set, so the
+// level and scale are the block's. The tile's digit counts go to its set's
+// rows of hist with one atomic per nonzero bin.
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_batch_keygen(
-    const P3b* __restrict__ xyz, uint32_t n, const uint64_t* __restrict__ set_off,
-    uint32_t n_sets, const uint8_t* __restrict__ set_level, uint32_t L_all,
+    const P3b* __restrict__ xyz, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ tile_set, const uint8_t* __restrict__ set_level, uint32_t L_all,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t n_pass,
-    uint32_t* __restrict__ hist, uint32_t* __restrict__ err, uint32_t chunk) {
+    uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
   __shared__ uint32_t s_hist[kMaxPasses * 256];
-  __shared__ uint32_t s_set0;
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256) s_hist[i] = 0;
-  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
-  const uint64_t end = min<uint64_t>(begin + chunk, n);
-  if (threadIdx.x == 0) s_set0 = find_set(set_off, n_sets, begin);
+  const uint32_t t = blockIdx.x;
+  const uint32_t begin = tile_start[t], end = tile_start[t + 1];
+  const uint32_t set = tile_set[t] & 0x7FFFFFFFu;
+  const uint32_t L = set_level[set];
+  const float scale = (float)(1u << L);
+  const uint32_t qmax = (1u << L) - 1;
+  const uint64_t high = (uint64_t)set << (3 * L_all);
+  const uint32_t lshift = 3 * (L_all - L);
   __syncthreads();
-  uint32_t set = s_set0;
   bool bad = false;
-  for (uint64_t i = begin + threadIdx.x; i < end; i += 256) {
-    while (set_off[set + 1] <= i) ++set;
-    const uint32_t L = set_level[set];
-    const float scale = (float)(1u << L);
-    const uint32_t qmax = (1u << L) - 1;
+  for (uint32_t i = begin + threadIdx.x; i < end; i += 256) {
     const P3b p = xyz[i];
     const bool ok = (p.x >= 0.0f && p.x < 1.0f) && (p.y >= 0.0f && p.y < 1.0f) &&
                     (p.z >= 0.0f && p.z < 1.0f);
@@ -67,34 +55,58 @@ __global__ __launch_bounds__(256) void k_batch_keygen(
       qz = min((uint32_t)floorf(p.z * scale), qmax);
     }
     const uint64_t morton = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-    const uint64_t key = ((uint64_t)set << (3 * L_all)) | (morton << (3 * (L_all - L)));
+    const uint64_t key = high | (morton << lshift);
     if (PACKED) {
-      keys[i] = (key << 32) | (uint32_t)i;
+      keys[i] = (key << 32) | i;
     } else {
       keys[i] = key;
-      vals[i] = (uint32_t)i;
+      vals[i] = i;
     }
     for (uint32_t p8 = 0; p8 < n_pass; ++p8)
       atomicAdd(&s_hist[p8 * 256 + ((key >> (8 * p8)) & 0xFF)], 1u);
   }
   if (bad) atomicOr(err, 1u);
   __syncthreads();
+  uint32_t* h = hist + (uint64_t)set * n_pass * 256;
   for (uint32_t i = threadIdx.x; i < n_pass * 256; i += 256)
-    if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+    if (s_hist[i]) atomicAdd(&h[i], s_hist[i]);
 }
 
-void launch_batch_keygen(const float* xyz, uint32_t n, const uint64_t* set_off, uint32_t n_sets,
-                         const uint8_t* set_level, uint32_t L_all, bool packed, uint64_t* keys,
-                         uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
-                         hipStream_t s) {
-  const uint32_t chunk = 256 * div_up(div_up(n, 2048), 256);
-  const uint32_t grid = div_up(n, chunk);
+void launch_batch_keygen(const float* xyz, const uint32_t* tile_start, const uint32_t* tile_set,
+                         uint32_t n_tiles, const uint8_t* set_level, uint32_t L_all, bool packed,
+                         uint64_t* keys, uint32_t* vals, uint32_t n_pass, uint32_t* hist,
+                         uint32_t* err, hipStream_t s) {
+  if (n_tiles == 0) return;
   if (packed)
-    hipLaunchKernelGGL(k_batch_keygen<true>, dim3(grid), dim3(256), 0, s, (const P3b*)xyz, n,
-                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err, chunk);
+    hipLaunchKernelGGL(k_batch_keygen<true>, dim3(n_tiles), dim3(256), 0, s, (const P3b*)xyz,
+                       tile_start, tile_set, set_level, L_all, keys, vals, n_pass, hist, err);
   else
-    hipLaunchKernelGGL(k_batch_keygen<false>, dim3(grid), dim3(256), 0, s, (const P3b*)xyz, n,
-                       set_off, n_sets, set_level, L_all, keys, vals, n_pass, hist, err, chunk);
+    hipLaunchKernelGGL(k_batch_keygen<false>, dim3(n_tiles), dim3(256), 0, s, (const P3b*)xyz,
+                       tile_start, tile_set, set_level, L_all, keys, vals, n_pass, hist, err);
+}
+
+// Block (i, p): exclusive scan of set i's pass-p histogram, offset by the
+// set's first element.
+__global__ __launch_bounds__(256) void k_batch_digit_offsets(const uint32_t* __restrict__ hist,
+                                                             const uint64_t* __restrict__ set_off,
+                                                             uint32_t n_pass,
+                                                             uint32_t* __restrict__ goff) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t set = blockIdx.x, p = blockIdx.y, d = threadIdx.x, lane = d & 63, w = d >> 6;
+  const uint64_t row = ((uint64_t)set * n_pass + p) * 256;
+  const uint32_t c = hist[row + d];
+  const uint32_t inc = wave_incl_scan(c);
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint32_t base = (uint32_t)set_off[set];
+  for (uint32_t i = 0; i < w; ++i) base += s_w[i];
+  goff[row + d] = base + inc - c;
+}
+
+void launch_batch_digit_offsets(const uint32_t* hist, const uint64_t* set_off, uint32_t n_sets,
+                                uint32_t n_pass, uint32_t* goff, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_digit_offsets, dim3(n_sets, n_pass), dim3(256), 0, s, hist, set_off,
+                     n_pass, goff);
 }
 
 // first[l * (n_sets + 1) + i] = rank of set i's first box at level l: the box

@@ -54,11 +54,26 @@ void launch_keygen(const float* xyz, uint32_t n, uint32_t L, bool packed, uint64
 void launch_reduce_rows(const uint32_t* rows, uint32_t n_rows, uint32_t* hist, uint32_t n_pass,
                         hipStream_t s);
 void launch_digit_offsets(const uint32_t* hist, uint32_t* goff, uint32_t n_pass, hipStream_t s);
+uint32_t sort_tile_elems(int items);
 uint32_t sort_tiles(uint32_t n, int items);
+// Many point sets sorted at once, each within its own range: tile t covers
+// elements [start[t], start[t + 1]) of set set[t] & 0x7FFFFFFF, never more
+// than one set (the top bit marks a set's first tile); goff holds, per set
+// and pass, where each digit's run starts (the set's first element included),
+// n_sets x n_pass x 256.
+struct SegSort {
+  const uint32_t* start;
+  const uint32_t* set;
+  const uint32_t* goff;
+  uint32_t n_tiles, n_pass, pass;
+};
 void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                       uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
                       uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
                       const uint32_t* n_dev = nullptr);  // n_dev: count on the device, n = capacity
+void launch_sort_pass_seg(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                          uint32_t* vout, uint32_t shift, const SegSort& sg, uint64_t* status,
+                          uint32_t* tile_counter, hipStream_t s, int items);
 
 // ---- tables.hip
 void launch_leaf(bool packed, bool key64, const uint64_t* sk, const uint32_t* sv,
@@ -176,10 +191,17 @@ void launch_dense_lists(bool key64, bool fill, uint32_t l, uint32_t n_up, const 
 struct LevelPtrs {
   const uint32_t* begin[kMaxLevel + 1];
 };
-void launch_batch_keygen(const float* xyz, uint32_t n, const uint64_t* set_off, uint32_t n_sets,
-                         const uint8_t* set_level, uint32_t L_all, bool packed, uint64_t* keys,
-                         uint32_t* vals, uint32_t n_pass, uint32_t* hist, uint32_t* err,
-                         hipStream_t s);
+// Composite keys of a batch, one block per tile of a set-aligned table of
+// 8192-element tiles (SegSort's start and set), and each set's digit counts
+// of the n_pass sort passes added into hist (zeroed, n_sets x n_pass x 256).
+void launch_batch_keygen(const float* xyz, const uint32_t* tile_start, const uint32_t* tile_set,
+                         uint32_t n_tiles, const uint8_t* set_level, uint32_t L_all, bool packed,
+                         uint64_t* keys, uint32_t* vals, uint32_t n_pass, uint32_t* hist,
+                         uint32_t* err, hipStream_t s);
+// goff[(i * n_pass + p) * 256 + d] = set_off[i] + the points of set i whose
+// pass-p digit is below d.
+void launch_batch_digit_offsets(const uint32_t* hist, const uint64_t* set_off, uint32_t n_sets,
+                                uint32_t n_pass, uint32_t* goff, hipStream_t s);
 void launch_batch_first(const LevelPtrs& lp, uint32_t L_all, const uint32_t* n_boxes,
                         const uint64_t* set_off, uint32_t n_sets, uint32_t* first, hipStream_t s);
 struct RebaseArgs {  // every level 0..L of a batch

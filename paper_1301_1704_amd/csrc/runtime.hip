@@ -13,6 +13,7 @@
 #include <atomic>
 #include <mutex>
 #include <tuple>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1129,6 +1130,7 @@ struct BatchImpl {
   uint32_t n_sets = 0, P = 0, L = 0, setbits = 0, keybits = 0, n_pass = 0;
   bool packed = false;
   int items = kSortItemsDefault;
+  bool items_fixed = false;  // set from FMMDS_BATCH_SORT_ITEMS: no timing
   std::vector<uint64_t> off;
   std::vector<uint8_t> lev;
   hipStream_t stream = nullptr;
@@ -1137,6 +1139,12 @@ struct BatchImpl {
   Pool mem;
   uint64_t* d_off = nullptr;
   uint8_t* d_lev = nullptr;
+  // set-aligned sort tiles, one table per tile size (kTileItems), in one block
+  uint32_t n_tiles[4] = {};
+  uint32_t* d_tiles = nullptr;
+  uint32_t* d_tstart[4] = {};
+  uint32_t* d_tset[4] = {};
+  uint32_t* d_goff = nullptr;  // per set and pass, where each digit's run starts
   SortBufs sb{};
   uint32_t* perm = nullptr;
   float* sxyz = nullptr;
@@ -1158,7 +1166,7 @@ struct BatchImpl {
   size_t hblock_b = 0;
   // zeroed per launch: dblock, histograms, digit offsets, tickets, status words
   char* ws = nullptr;
-  size_t ws_b = 0, hist_at = 0, goffd_at = 0, tick_at = 0, words_at = 0;
+  size_t ws_b = 0, hist_at = 0, tick_at = 0, words_at = 0;
   size_t n_words = 0, n_tickets = 0, list_words = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1177,16 +1185,21 @@ struct BatchImpl {
   }
 };
 
+// The sort tile sizes a batch may use (the autotuned choice indexes them).
+constexpr int kTileItems[4] = {8, 12, 16, kSortWide};
+int tile_kind(int items) { return items == 8 ? 0 : items == 12 ? 1 : items == 16 ? 2 : 3; }
+
 void batch_sort_passes(BatchImpl& B, StatusArena& sa, Prof& P, int items) {
-  uint32_t* goffd = (uint32_t*)(B.ws + B.goffd_at);
+  const int kd = tile_kind(items);
   for (uint32_t p = 0; p < B.n_pass; ++p) {
     const int a = p & 1, b = a ^ 1;
     const uint32_t shift = (B.packed ? 32 : 0) + 8 * p;
-    uint64_t* stw = sa.take_words((size_t)sort_tiles(B.P, items) * 256);
+    uint64_t* stw = sa.take_words((size_t)B.n_tiles[kd] * 256);
     uint32_t* tk = sa.take_ticket();
+    const SegSort sg{B.d_tstart[kd], B.d_tset[kd], B.d_goff, B.n_tiles[kd], B.n_pass, p};
     P.run(K_SORT, (double)B.P * (B.packed ? 16 : 24), [&] {
-      launch_sort_pass(B.packed, B.sb.k[a], B.sb.k[b], B.sb.v[a], B.sb.v[b], B.P, shift,
-                       goffd + p * 256, stw, tk, B.stream, items);
+      launch_sort_pass_seg(B.packed, B.sb.k[a], B.sb.k[b], B.sb.v[a], B.sb.v[b], shift, sg, stw,
+                           tk, B.stream, items);
     });
   }
 }
@@ -1200,16 +1213,18 @@ void batch_front(BatchImpl& B, const float* xyz, StatusArena& sa, Prof& P, int i
   sa.n_words = B.n_words;
   // only the status words this launch takes (the sort's depend on its tile
   // size; the workspace is sized for the smallest tiles)
-  const size_t used = (size_t)B.n_pass * sort_tiles(B.P, items) * 256 + B.list_words;
+  const size_t used = (size_t)B.n_pass * B.n_tiles[tile_kind(items)] * 256 + B.list_words;
   const size_t zb = std::min(B.ws_b, round_up(B.words_at + used * 8, 256));
   P.run(K_ZERO, (double)zb, [&] { launch_zero(B.ws, zb, st); });
   uint32_t* hist = (uint32_t*)(B.ws + B.hist_at);
-  uint32_t* goffd = (uint32_t*)(B.ws + B.goffd_at);
+  const int kw = tile_kind(kSortWide);  // keygen tiles: 8192 points
   P.run(K_KEYGEN, (double)B.P * (12 + 8 + (B.packed ? 0 : 4)), [&] {
-    launch_batch_keygen(xyz, B.P, B.d_off, B.n_sets, B.d_lev, B.L, B.packed, B.sb.k[0],
-                        B.sb.v[0], B.n_pass, hist, &B.meta()->err_range, st);
+    launch_batch_keygen(xyz, B.d_tstart[kw], B.d_tset[kw], B.n_tiles[kw], B.d_lev, B.L, B.packed,
+                        B.sb.k[0], B.sb.v[0], B.n_pass, hist, &B.meta()->err_range, st);
   });
-  P.run(K_DIGITS, (double)B.n_pass * 2048, [&] { launch_digit_offsets(hist, goffd, B.n_pass, st); });
+  P.run(K_DIGITS, (double)B.n_sets * B.n_pass * 2048, [&] {
+    launch_batch_digit_offsets(hist, B.d_off, B.n_sets, B.n_pass, B.d_goff, st);
+  });
 }
 
 void batch_enqueue(BatchImpl& B, const float* xyz, Prof& P) {
@@ -1409,7 +1424,14 @@ fmmds_status batch_plan(const uint64_t* set_offsets, const uint8_t* levels, uint
   B.setbits = setbits;
   B.keybits = setbits + 3 * L;
   B.packed = B.keybits <= 32;
-  B.n_pass = div_up(B.keybits, 8);
+  // each set is sorted within its own range: only the Morton bits are digits
+  B.n_pass = div_up(3 * L, 8);
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t T = sort_tile_elems(kTileItems[k]);
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < n_sets; ++i) t += (set_offsets[i + 1] - set_offsets[i] + T - 1) / T;
+    B.n_tiles[k] = (uint32_t)t;
+  }
   for (uint32_t l = 0; l <= L; ++l) {
     uint64_t c = 0, r = 0;
     for (uint32_t i = 0; i < n_sets; ++i) {
@@ -1426,11 +1448,47 @@ fmmds_status batch_plan(const uint64_t* set_offsets, const uint8_t* levels, uint
   return FMMDS_OK;
 }
 
+// Words of the set-aligned tile tables: per tile size, start (n_tiles + 1)
+// then set (n_tiles).
+size_t tile_table_words(const BatchImpl& B) {
+  size_t w = 0;
+  for (int k = 0; k < 4; ++k) w += 2 * (size_t)B.n_tiles[k] + 1;
+  return w;
+}
+
+// Fills the tables tile_table_words describes: tiles of sort_tile_elems
+// elements laid over each set in turn (the last one of a set ragged), each
+// tile's set with the top bit set on a set's first tile.
+void fill_tile_tables(const BatchImpl& B, uint32_t* out) {
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t T = sort_tile_elems(kTileItems[k]);
+    uint32_t* start = out;
+    uint32_t* set = out + B.n_tiles[k] + 1;
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < B.n_sets; ++i)
+      for (uint64_t e = B.off[i]; e < B.off[i + 1]; e += T, ++t) {
+        start[t] = (uint32_t)e;
+        set[t] = i | (e == B.off[i] ? 0x80000000u : 0u);
+      }
+    start[t] = B.P;
+    out += 2 * (size_t)B.n_tiles[k] + 1;
+  }
+}
+
 // Every device buffer of a planned batch, carved from one block.
 void batch_layout(BatchImpl& B, Carve& M) {
   const uint32_t n_sets = B.n_sets, P = B.P, L = B.L;
   B.d_off = M.get<uint64_t>(n_sets + 1);
   B.d_lev = M.get<uint8_t>(n_sets);
+  B.d_tiles = M.get<uint32_t>(tile_table_words(B));
+  size_t o = 0;
+  for (int k = 0; k < 4; ++k) {
+    B.d_tstart[k] = B.d_tiles ? B.d_tiles + o : nullptr;
+    o += B.n_tiles[k] + 1;
+    B.d_tset[k] = B.d_tiles ? B.d_tiles + o : nullptr;
+    o += B.n_tiles[k];
+  }
+  B.d_goff = M.get<uint32_t>((size_t)n_sets * B.n_pass * 256);
   B.sb.k[0] = M.get<uint64_t>(P);
   B.sb.k[1] = M.get<uint64_t>(P);
   B.sb.v[0] = B.sb.v[1] = nullptr;
@@ -1473,13 +1531,13 @@ void batch_layout(BatchImpl& B, Carve& M) {
   B.base_at = round_up(B.first_at + (size_t)(L + 1) * (n_sets + 1) * 4, 256);
   B.dblock_b = round_up(B.base_at + (size_t)(L + 1) * 2 * (n_sets + 1) * 4, 256);
   B.hist_at = B.dblock_b;
-  B.goffd_at = B.hist_at + round_up(kMaxPasses * 256 * 4, 256);
-  B.tick_at = B.goffd_at + round_up(kMaxPasses * 256 * 4, 256);
+  B.tick_at = B.hist_at + round_up((size_t)n_sets * B.n_pass * 256 * 4, 256);
   B.n_tickets = B.n_pass + 1 + L + 2 * (L + 1);
   B.words_at = B.tick_at + round_up(B.n_tickets * 4, 256);
   B.list_words = 0;
   for (uint32_t l = 2; l <= L; ++l) B.list_words += 2 * (size_t)scan_tiles(B.cap[l]);
-  const size_t words = (size_t)B.n_pass * sort_tiles(P, 8) * 256 + B.list_words;
+  const size_t words =
+      (size_t)B.n_pass * *std::max_element(B.n_tiles, B.n_tiles + 4) * 256 + B.list_words;
   B.n_words = words;
   B.ws_b = round_up(B.words_at + words * 8, 256);
   B.ws = M.get<char>(B.ws_b);
@@ -1502,6 +1560,13 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
   try {
     B->off.assign(set_offsets, set_offsets + n_sets + 1);
     B->lev.assign(levels, levels + n_sets);
+    if (const char* e = std::getenv("FMMDS_BATCH_SORT_ITEMS")) {
+      const int v = std::atoi(e);
+      if (v == 8 || v == 12 || v == 16 || (v == kSortWide && B->packed)) {
+        B->items = v;
+        B->items_fixed = true;
+      }
+    }
     if (opt->stream) {
       B->stream = (hipStream_t)opt->stream;
     } else {
@@ -1522,14 +1587,19 @@ fmmds_status batch_create(const uint64_t* set_offsets, const uint8_t* levels, ui
     // staged for an asynchronous upload (it lives as long as the batch).
     const size_t stage_off = round_up(B->dblock_b, 256);
     const size_t stage_lev = stage_off + round_up((n_sets + 1) * 8, 256);
-    B->hblock_b = stage_lev + n_sets;
+    const size_t stage_tiles = stage_lev + round_up(n_sets, 256);
+    const size_t tiles_b = tile_table_words(*B) * 4;
+    B->hblock_b = stage_tiles + tiles_b;
     B->hblock = (char*)pinned_alloc(B->hblock_b);
     if (!B->hblock) throw Fail{FMMDS_ERR_NOMEM};
     std::memcpy(B->hblock + stage_off, set_offsets, (n_sets + 1) * 8);
     std::memcpy(B->hblock + stage_lev, levels, n_sets);
+    fill_tile_tables(*B, (uint32_t*)(B->hblock + stage_tiles));
     ck(hipMemcpyAsync(B->d_off, B->hblock + stage_off, (n_sets + 1) * 8, hipMemcpyHostToDevice,
                       B->stream));
     ck(hipMemcpyAsync(B->d_lev, B->hblock + stage_lev, n_sets, hipMemcpyHostToDevice, B->stream));
+    ck(hipMemcpyAsync(B->d_tiles, B->hblock + stage_tiles, tiles_b, hipMemcpyHostToDevice,
+                      B->stream));
     B->trees.assign(n_sets, fmmds_tree());
     B->views.resize(n_sets);
     for (uint32_t i = 0; i < n_sets; ++i) B->views[i].view = true;
@@ -1578,7 +1648,7 @@ fmmds_status batch_launch(BatchImpl* B, const float* xyz, int capture) {
     if (capture) {
       if (B->exec && B->graph_xyz != xyz) return FMMDS_ERR_ARG;
       if (!B->exec) {
-        B->items = batch_autotune(*B, xyz);
+        if (!B->items_fixed) B->items = batch_autotune(*B, xyz);
         Prof off;
         ck(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
         try {
@@ -1594,7 +1664,7 @@ fmmds_status batch_launch(BatchImpl* B, const float* xyz, int capture) {
         B->graph_xyz = xyz;
       }
       ck(hipGraphLaunch(B->exec, B->stream));
-    } else {
+    } else if (!B->items_fixed) {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(TuneKey{(uint32_t)(63 - __builtin_clzll((uint64_t)B->P | 1)),
                                     B->n_pass, B->packed ? 1u : 0u});

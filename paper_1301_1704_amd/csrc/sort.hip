@@ -177,12 +177,15 @@ __device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t shift) {
                 : (uint32_t)(k >> shift) & 0xFFu;
 }
 
-template <bool PACKED, int BLOCK, int ITEMS>
+// With SEG, tiles come from a set-aligned table (SegSort): each tile lies in
+// one set, a set's first tile starts its own look-back chain, and the digit
+// offsets are that set's, so every set is sorted within its own range.
+template <bool PACKED, int BLOCK, int ITEMS, bool SEG>
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ vout, uint32_t n_host, uint32_t shift, const uint32_t* __restrict__ goff,
     uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
-    const uint32_t* __restrict__ n_dev) {
+    const uint32_t* __restrict__ n_dev, SegSort sg) {
   static_assert(BLOCK >= 256, "thread d owns digit d");
   constexpr int W = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
@@ -197,19 +200,33 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   __shared__ uint32_t s_tile;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t n = n_dev ? *n_dev : n_host;
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   for (uint32_t i = tid; i < W * 256; i += BLOCK) (&s_hist[0][0])[i] = 0;
   if (tid < 256) s_cnt[tid] = 0;
   __syncthreads();
-  const uint32_t tile = s_tile;
-  // With the count on the device the grid covers the capacity; tiles past
-  // the count exit (tiles only look back at lower tile ids).
-  if ((uint64_t)tile * TILE >= n && tile > 0) return;
-  const uint64_t wbase = (uint64_t)tile * TILE + (uint64_t)w * WSEG;
+  const uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
+  uint64_t tbase, tend;
+  bool first;
+  const uint32_t* __restrict__ go = goff;
+  if (SEG) {
+    tbase = sg.start[tile];
+    tend = sg.start[tile + 1];
+    const uint32_t sw = sg.set[tile];
+    first = (sw >> 31) != 0;
+    go = sg.goff + ((uint64_t)(sw & 0x7FFFFFFFu) * sg.n_pass + sg.pass) * 256;
+  } else {
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    // With the count on the device the grid covers the capacity; tiles past
+    // the count exit (tiles only look back at lower tile ids).
+    if ((uint64_t)tile * TILE >= n && tile > 0) return;
+    tbase = (uint64_t)tile * TILE;
+    tend = min(tbase + TILE, (uint64_t)n);
+    first = tile == 0;
+  }
+  const uint64_t wbase = tbase + (uint64_t)w * WSEG;
   // Item i of this lane is element wbase + 64 i + lane, valid while
   // 64 i + lane < lim (32-bit tests; the wave's base pointer is uniform).
-  const uint32_t lim = (uint32_t)min((uint64_t)WSEG, n > wbase ? (uint64_t)n - wbase : 0ull);
+  const uint32_t lim = (uint32_t)min((uint64_t)WSEG, tend > wbase ? tend - wbase : 0ull);
   const uint64_t* __restrict__ kw = kin + wbase;
   const uint32_t* __restrict__ vw = PACKED ? nullptr : vin + wbase;
 
@@ -230,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
   __syncthreads();
   if (tid < 256) {
     const uint64_t agg = s_cnt[tid];
-    st_status(status + (uint64_t)tile * 256 + tid, (tile == 0 ? kStInc : kStAgg) | agg);
+    st_status(status + (uint64_t)tile * 256 + tid, (first ? kStInc : kStAgg) | agg);
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -279,8 +296,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     for (uint32_t ww = 0; ww < w; ++ww) wpre += s_scan[ww];
     const uint32_t lstart = wpre + inc - cnt;
     s_lstart[d] = lstart;
-    const uint64_t excl = lookback_window<4>(status + d, 256, tile, cnt);
-    s_base[d] = goff[d] + (uint32_t)excl - lstart;
+    const uint64_t excl = first ? 0 : lookback_window<4>(status + d, 256, tile, cnt);
+    s_base[d] = go[d] + (uint32_t)excl - lstart;
   }
   __syncthreads();
 
@@ -294,8 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(
     }
   }
   __syncthreads();
-  const uint64_t tbase = (uint64_t)tile * TILE;
-  const uint32_t tcount = (uint32_t)min((uint64_t)TILE, (uint64_t)n - tbase);
+  const uint32_t tcount = (uint32_t)(tend - tbase);
   for (uint32_t j = tid; j < tcount; j += BLOCK) {
     const uint64_t kk = s_key[j];
     const uint32_t dd = sort_digit<PACKED>(kk, shift);
@@ -309,14 +325,14 @@ uint32_t sort_tile_elems(int items) { return items == kSortWide ? 8192u : 256u *
 
 uint32_t sort_tiles(uint32_t n, int items) { return div_up(n, sort_tile_elems(items)); }
 
-void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
-                      uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
-                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
-                      const uint32_t* n_dev) {
-  const uint32_t grid = sort_tiles(n, items);
+template <bool SEG>
+void sort_pass_dispatch(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                        uint32_t* vout, uint32_t n, uint32_t grid, uint32_t shift,
+                        const uint32_t* goff, uint64_t* status, uint32_t* tile_counter,
+                        hipStream_t s, int items, const uint32_t* n_dev, const SegSort& sg) {
 #define FMMDS_SORT(P, B, I)                                                                     \
-  hipLaunchKernelGGL((k_sort_pass<P, B, I>), dim3(grid), dim3(B), 0, s, kin, kout, vin, vout,  \
-                     n, shift, goff, status, tile_counter, n_dev)
+  hipLaunchKernelGGL((k_sort_pass<P, B, I, SEG>), dim3(grid), dim3(B), 0, s, kin, kout, vin,   \
+                     vout, n, shift, goff, status, tile_counter, n_dev, sg)
   if (items == kSortWide && packed) FMMDS_SORT(true, 512, 16);
   else if (items == 8) {
     if (packed) FMMDS_SORT(true, 256, 8);
@@ -329,6 +345,22 @@ void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const ui
     else FMMDS_SORT(false, 256, 16);
   }
 #undef FMMDS_SORT
+}
+
+void launch_sort_pass(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                      uint32_t* vout, uint32_t n, uint32_t shift, const uint32_t* goff,
+                      uint64_t* status, uint32_t* tile_counter, hipStream_t s, int items,
+                      const uint32_t* n_dev) {
+  sort_pass_dispatch<false>(packed, kin, kout, vin, vout, n, sort_tiles(n, items), shift, goff,
+                            status, tile_counter, s, items, n_dev, SegSort{});
+}
+
+void launch_sort_pass_seg(bool packed, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                          uint32_t* vout, uint32_t shift, const SegSort& sg, uint64_t* status,
+                          uint32_t* tile_counter, hipStream_t s, int items) {
+  if (sg.n_tiles == 0) return;
+  sort_pass_dispatch<true>(packed, kin, kout, vin, vout, 0, sg.n_tiles, shift, nullptr, status,
+                           tile_counter, s, items, nullptr, sg);
 }
 
 }  // namespace fmmds

@@ -203,3 +203,58 @@ def test_batch_full_512_sets_sampled(F, oracle_lib):
         o = oracle_lib.OracleTree(pts, None, key_bits=64, max_level=int(lev[i]))
         _compare_set(b.tree(i), o)
     b.free()
+
+
+def _tile_edge_batch(sizes, levels, seed):
+    parts = [I.uniform_points(seed + i, n) if i % 2 == 0 else
+             I.cluster_points(seed + i, n, I.cluster_centres(seed + i, 4), 0.02)
+             for i, n in enumerate(sizes)]
+    off = np.zeros(len(parts) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    return (parts, np.ascontiguousarray(np.concatenate(parts, axis=0)), off,
+            np.asarray(levels, dtype=np.uint8))
+
+
+@pytest.mark.parametrize("items", [8, 12, 16, 32])
+def test_batch_every_sort_tile_size(F, oracle_lib, monkeypatch, items):
+    """Each sort tile size, fixed through FMMDS_BATCH_SORT_ITEMS, on sets
+    that fill one partial tile, exactly one or two tiles, or several tiles
+    and a ragged tail (the sort's tiles never straddle two sets): every set
+    against the oracle, eagerly and through a graph replay."""
+    sizes = [1, 7, 2047, 2048, 2049, 3072, 4096, 8192, 8197, 20001, 3, 16384]
+    levels = [2, 3, 4, 4, 5, 3, 4, 5, 5, 6, 2, 4]
+    parts, xyz, off, lev = _tile_edge_batch(sizes, levels, 40)
+    monkeypatch.setenv("FMMDS_BATCH_SORT_ITEMS", str(items))
+    b = F.Batch(off, lev)
+    assert b.sort_items == items
+    x = parity.to_gpu(xyz)
+    for capture in (False, True):
+        b.launch(x, capture=capture)
+        b.wait()
+        assert b.sort_items == items
+        for i, pts in enumerate(parts):
+            o = oracle_lib.OracleTree(pts, None, key_bits=64, max_level=int(lev[i]))
+            _compare_set(b.tree(i), o)
+    b.free()
+
+
+@pytest.mark.parametrize("items", [8, 16])
+def test_batch_keys_over_32_bits(F, oracle_lib, monkeypatch, items):
+    """600 sets, one of them at level 8: composite keys of 10 + 24 bits, so
+    keys and point indices sort as separate arrays."""
+    rng = np.random.default_rng(9)
+    sizes = [int(v) for v in rng.integers(1, 40, 600)]
+    sizes[3] = 6000
+    sizes[599] = 2500
+    levels = [2 + (i % 3) for i in range(600)]
+    levels[3] = 8
+    parts, xyz, off, lev = _tile_edge_batch(sizes, levels, 70)
+    monkeypatch.setenv("FMMDS_BATCH_SORT_ITEMS", str(items))
+    b = F.Batch(off, lev)
+    assert b.sort_items == items
+    b.launch(parity.to_gpu(xyz))
+    b.wait()
+    for i in sorted({0, 1, 2, 3, 4, 300, 598, 599} | set(rng.integers(0, 600, 12).tolist())):
+        o = oracle_lib.OracleTree(parts[i], None, key_bits=64, max_level=int(lev[i]))
+        _compare_set(b.tree(i), o)
+    b.free()
