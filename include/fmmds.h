@@ -246,8 +246,8 @@ uint64_t fmmds_batch_bytes(const fmmds_batch* b);
  * (tiles of 256 threads with that many elements each) or 32 (8192 elements,
  * 512 threads). A graph capture times the four and keeps the fastest; the
  * environment variable FMMDS_BATCH_SORT_ITEMS, read by fmmds_batch_create,
- * fixes it instead (8, 12, 16, or 32 when ceil(log2 n_sets) + 3 times the
- * deepest level is at most 32; other values are ignored). */
+ * fixes it instead (8, 12, 16, or 32 when max(1, ceil(log2 n_sets)) plus 3
+ * times the deepest level is at most 32; other values are ignored). */
 uint32_t fmmds_batch_sort_items(const fmmds_batch* b);
 void fmmds_batch_free(fmmds_batch* b);
 
