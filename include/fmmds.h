@@ -213,7 +213,7 @@ void fmmds_free(fmmds_tree* t);
  * fmmds_batch_create plans one batch shape and allocates every buffer for
  * the worst case of that shape (no host synchronization is needed later):
  *   set_offsets: host, n_sets + 1 point offsets, set_offsets[0] = 0, strictly
- *                increasing (no empty set), total < 2^32 - 1.
+ *                increasing (no empty set), total < 2^32 - 1; n_sets < 2^31.
  *   levels:      host, n_sets max levels in [2, 21].
  *   opt:         host; key_bits must be 64, cluster_s 0; stream and allocator
  *                as for fmmds_build.

@@ -1164,7 +1164,7 @@ struct BatchImpl {
   size_t dblock_b = 0, first_at = 0, base_at = 0;
   char* hblock = nullptr;  // pinned mirror, followed by the staged offsets and levels
   size_t hblock_b = 0;
-  // zeroed per launch: dblock, histograms, digit offsets, tickets, status words
+  // zeroed per launch: dblock, the sets' digit histograms, tickets, status words
   char* ws = nullptr;
   size_t ws_b = 0, hist_at = 0, tick_at = 0, words_at = 0;
   size_t n_words = 0, n_tickets = 0, list_words = 0;
@@ -1407,7 +1407,9 @@ struct Carve {
 // min(n_i, 8^min(l, L_i))).
 fmmds_status batch_plan(const uint64_t* set_offsets, const uint8_t* levels, uint32_t n_sets,
                         BatchImpl& B) {
-  if (!set_offsets || !levels || n_sets == 0 || set_offsets[0] != 0) return FMMDS_ERR_ARG;
+  // (set ids are 31 bits in the sort's tile tables)
+  if (!set_offsets || !levels || n_sets == 0 || n_sets >= 0x80000000u || set_offsets[0] != 0)
+    return FMMDS_ERR_ARG;
   uint32_t L = 0;
   for (uint32_t i = 0; i < n_sets; ++i) {
     if (set_offsets[i + 1] <= set_offsets[i]) return FMMDS_ERR_ARG;

@@ -107,3 +107,29 @@ def test_rebuild_arguments_rejected_on_host(lib):
     t.src_perm = None
     assert lib.fmmds_rebuild(C.byref(t), fake, None, 0, C.byref(ok), C.byref(out)) == F.ERR_ARG
     assert not out
+
+
+def test_batch_footprint_plans_on_host(lib):
+    """fmmds_batch_footprint runs the batch plan and layout on the host: it
+    grows with the points and the levels, and rejects bad shapes, among them
+    2^31 sets or more (set ids are 31 bits in the sort's tile tables; checked
+    before the offsets are read)."""
+    import numpy as np
+    import paper_1301_1704_amd as F
+
+    def footprint(off, lev, n_sets=None):
+        off = np.ascontiguousarray(off, dtype=np.uint64)
+        lev = np.ascontiguousarray(lev, dtype=np.uint8)
+        b = C.c_uint64(0)
+        st = lib.fmmds_batch_footprint(off.ctypes.data_as(C.c_void_p),
+                                       lev.ctypes.data_as(C.c_void_p),
+                                       len(lev) if n_sets is None else n_sets, C.byref(b))
+        return st, b.value
+
+    st1, b1 = footprint([0, 1000, 3000], [3, 4])
+    st2, b2 = footprint([0, 1000, 300000], [3, 6])
+    assert st1 == F.OK and st2 == F.OK and 0 < b1 < b2
+    assert footprint([0, 1000, 1000], [3, 4])[0] == F.ERR_ARG    # an empty set
+    assert footprint([0, 1000], [1])[0] == F.ERR_ARG             # level below 2
+    assert footprint([0, 1000], [3], n_sets=2 ** 31)[0] == F.ERR_ARG
+    assert footprint([0, 1000], [3], n_sets=0)[0] == F.ERR_ARG
