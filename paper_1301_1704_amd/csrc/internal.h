@@ -127,6 +127,7 @@ struct ListLevelArgs {
   uint32_t key_bits_up;         // bits of the level - 1 keys including the set id
   const uint32_t* n_recv_up_dev;// if set, the parent count is read here and
                                 // n_recv_up is only the capacity
+  const uint32_t* n_src_up_dev; // if set (up_all), the level - 1 source count
   // Fill only: with cnt2_next set, the fill also writes the E2 / E4 counts of
   // the receiver boxes of level + 1 (what the count kernel would compute
   // there), from the lists it builds for their parents.

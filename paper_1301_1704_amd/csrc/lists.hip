@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_list_count(ListLevelArgs a, uint32_t* _
   uint32_t j0, cnt, upbase = 0;
   if (a.up_all) {
     j0 = 0;
-    cnt = a.n_src_up;
+    cnt = a.n_src_up_dev ? *a.n_src_up_dev : a.n_src_up;
   } else {
     j0 = a.e2_off_up[p];
     cnt = a.e2_off_up[p + 1] - j0;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_list_fill(ListLevelArgs a, const uint32
   bool next_zero = false;  // the set has no lists at level + 1
   if (live) {
     if (a.up_all) {
-      cnt = a.n_src_up;
+      cnt = a.n_src_up_dev ? *a.n_src_up_dev : a.n_src_up;
     } else {
       j0 = a.e2_off_up[p];
       cnt = a.e2_off_up[p + 1] - j0;

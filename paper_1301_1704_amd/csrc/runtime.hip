@@ -358,7 +358,7 @@ std::mutex g_prof_mu;
 ClassStat g_prof[K_NCLASS];
 std::vector<hipEvent_t> g_events;  // reusable, guarded by g_prof_mu
 
-constexpr int kListSet = 2;  // Prof record tag: a list fill of level `level`
+constexpr int kListSet = 2;  // Prof record tag: a list kernel (count, scan, fill) of `level`
 
 struct Prof {
   bool on = false;
@@ -852,10 +852,16 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       if (e1->ev) ck(hipStreamWaitEvent(st, e1->ev, 0));
     }
 
-    // ---- sync point 1: box counts, range flag, occupancy maxima
+    // ---- sync point 1: box counts, range flag, occupancy maxima. A plain
+    // build without the depth rule skips it: its list kernels read the box
+    // counts on the device over grids sized by capacity, and the range flag
+    // and the counts come back at the finest level's sync.
+    const bool early = plain && opt->cluster_s == 0 && L >= 2;
     DevMeta* hm = host_meta();
-    fetch_meta(meta, hm, st);
-    if (hm->err_range) throw Fail{FMMDS_ERR_RANGE};
+    if (!early) {
+      fetch_meta(meta, hm, st);
+      if (hm->err_range) throw Fail{FMMDS_ERR_RANGE};
+    }
     const int rs = shared ? 0 : 1;
     uint32_t D = L;
     if (opt->cluster_s > 0) {
@@ -866,9 +872,21 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
         }
       }
     }
-    uint32_t nb[2][kMaxLevel + 1];
+    // nb: box counts (capacities until known, in the early case); lcap: the
+    // sizes the lists' buffers and grids are laid out with (fixed from here)
+    uint32_t nb[2][kMaxLevel + 1], lcap[2][kMaxLevel + 1];
+    auto read_counts = [&]() {
+      for (int s = 0; s < 2; ++s)
+        for (uint32_t l = 0; l <= L; ++l) nb[s][l] = hm->n_boxes[s < nsets ? s : 0][l];
+    };
+    if (early) {
+      for (int s = 0; s < 2; ++s)
+        for (uint32_t l = 0; l <= L; ++l) nb[s][l] = level_cap(sets[s < nsets ? s : 0].n, l);
+    } else {
+      read_counts();
+    }
     for (int s = 0; s < 2; ++s)
-      for (uint32_t l = 0; l <= L; ++l) nb[s][l] = hm->n_boxes[s < nsets ? s : 0][l];
+      for (uint32_t l = 0; l <= L; ++l) lcap[s][l] = nb[s][l];
 
     // Dense variant: the point order. Boxes of up to kDenseCanonMax points
     // are put in index order on the device; beyond that the set's points are
@@ -917,8 +935,8 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // ---- lists, levels 2..D
     size_t lwords = 0, lmax = 0;
     for (uint32_t l = 2; l <= D; ++l) {
-      lwords += 2 * (size_t)scan_tiles(nb[rs][l]);
-      lmax = std::max<size_t>(lmax, nb[rs][l]);
+      lwords += 2 * (size_t)scan_tiles(lcap[rs][l]);
+      lmax = std::max<size_t>(lmax, lcap[rs][l]);
     }
     const size_t ltick_b = round_up(2 * (kMaxLevel + 1) * 4, 256);
     const size_t lws_b = round_up(ltick_b + lwords * 8, 256);
@@ -936,7 +954,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // receiver box) and need no host round trip for their totals, which are
     // read at the next one; the finest level is allocated exactly.
     auto small_level = [&](uint32_t l) {
-      return l < D && (uint64_t)nb[rs][l] * 4 <= (uint64_t)nb[rs][D];
+      return l < D && (uint64_t)lcap[rs][l] * 4 <= (uint64_t)lcap[rs][D];
     };
     auto take_totals = [&](const DevMeta* h, uint32_t upto) {
       for (uint32_t m = 2; m <= upto; ++m)
@@ -948,7 +966,7 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
     // each, less than an allocator call and a launch take on the host).
     size_t lblock_b = 0;
     for (uint32_t l = 2; l <= D; ++l) {
-      const size_t nr = nb[rs][l];
+      const size_t nr = lcap[rs][l];
       lblock_b += 2 * round_up((nr + 1) * 4, 256);
       if (small_level(l)) lblock_b += round_up(27 * nr * 4, 256) + round_up(189 * nr * 4, 256);
     }
@@ -959,10 +977,14 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       return q;
     };
     for (uint32_t l = 2; l <= D; ++l) {
-      const uint32_t nr = nb[rs][l];
+      const uint32_t nr = lcap[rs][l];
       ListLevelArgs a{};
       a.level = l;
-      a.n_recv_up = nb[rs][l - 1];
+      a.n_recv_up = lcap[rs][l - 1];
+      if (early) {
+        a.n_recv_up_dev = &meta->n_boxes[rs][l - 1];
+        a.n_src_up_dev = &meta->n_boxes[0][l - 1];
+      }
       a.recv_key_up = sets[rs].lv[l - 1].key;
       a.recv_mask_up = sets[rs].lv[l - 1].mask;
       a.recv_child_up = sets[rs].lv[l - 1].child;
@@ -970,18 +992,15 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
       a.src_mask_up = sets[0].lv[l - 1].mask;
       a.src_child_up = sets[0].lv[l - 1].child;
       a.up_all = (l - 1 == 1) ? 1u : 0u;
-      a.n_src_up = nb[0][l - 1];
+      a.n_src_up = lcap[0][l - 1];
       a.key_bits_up = 3 * (l - 1);
       if (!a.up_all) {
         a.e2_off_up = impl->lists[l - 1].off[0];
         a.e2_ent_up = impl->lists[l - 1].ent[0];
       }
       ListBufs& LB = impl->lists[l];
-      // receiver key + parent in, two counts out; the parent lists and the
-      // parent-level source keys, masks and first children read once (the
-      // list sizes are added once known, see P.finish below)
-      const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) +
-                          (double)nb[0][l - 1] * (ksz + 1 + 4);
+      // (the bytes of the count, scan and fill launches follow from the box
+      // counts and list sizes, added once known: see P.finish below)
       // level 2 only: the fill of each level writes the next level's counts
       if (dense)
         P.run(K_DLIST, 0.0, [&] {
@@ -991,23 +1010,28 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
                              nullptr, nullptr, nullptr, st);
         });
       else if (l == 2)
-        P.run(K_COUNT, side + (double)nr * 8,
-              [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); });
+        P.run(K_COUNT, 0.0, [&] { launch_list_count(key64, a, cnt, cnt + round_up(nr, 4), st); },
+              kListSet, (int)l);
       LB.off[0] = carve((size_t)nr + 1);
       LB.off[1] = carve((size_t)nr + 1);
       {
         uint64_t* st2 = la.take_words(scan_tiles(nr));
         uint64_t* st4 = la.take_words(scan_tiles(nr));
         uint32_t* tk = la.take_ticket();
-        P.run(K_SCAN, (double)nr * 16 + 8, [&] {
+        P.run(K_SCAN, 0.0, [&] {
           launch_scan_counts2(cnt, cnt + round_up(nr, 4), nr, LB.off[0], LB.off[1], &meta->list_total[0][l],
-                              &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st);
-        });
+                              &meta->list_total[1][l], &meta->overflow, st2, st4, tk, st,
+                              early ? &meta->n_boxes[rs][l] : nullptr);
+        }, kListSet, (int)l);
       }
       if (small_level(l)) {
         for (int k = 0; k < 2; ++k) LB.ent[k] = carve((size_t)nr * (k == 0 ? 27 : 189));
       } else {
         fetch_meta(meta, hm, st);  // sync point: this level's list totals
+        if (early) {
+          if (hm->err_range) throw Fail{FMMDS_ERR_RANGE};
+          read_counts();
+        }
         if (hm->overflow) throw Fail{FMMDS_ERR_OVERFLOW};
         take_totals(hm, l);
         for (int k = 0; k < 2; ++k) LB.ent[k] = impl->outs.get<uint32_t>(LB.total[k]);
@@ -1019,32 +1043,42 @@ fmmds_status build(const float* src_xyz, uint32_t n_src, const float* recv_xyz, 
                              dn[0].bin[l], dn[0].srank[l], nullptr, nullptr, LB.off[0],
                              LB.off[1], LB.ent[0], LB.ent[1], st);
         });
-        impl->n_recv_boxes[l] = nr;
         continue;
       }
-      double next_b = 0.0;  // level + 1 counts: masks and first children in, two counts out
-      if (l < D) {
+      if (l < D) {  // the next level's counts
         a.src_mask_cur = sets[0].lv[l].mask;
         a.recv_mask_cur = sets[rs].lv[l].mask;
         a.recv_child_cur = sets[rs].lv[l].child;
         a.cnt2_next = cnt;
-        a.cnt4_next = cnt + round_up(nb[rs][l + 1], 4);
-        next_b = (double)nr * 5 + (double)nb[0][l] + (double)nb[rs][l + 1] * 8;
+        a.cnt4_next = cnt + round_up(lcap[rs][l + 1], 4);
       }
-      P.run(K_FILL, side + (double)nr * 8 + next_b,
+      P.run(K_FILL, 0.0,
             [&] { launch_list_fill(key64, a, LB.off[0], LB.off[1], LB.ent[0], LB.ent[1], st); },
             kListSet, (int)l);
-      impl->n_recv_boxes[l] = nr;
     }
+    for (uint32_t l = 2; l <= D; ++l) impl->n_recv_boxes[l] = nb[rs][l];
 
     // Box-count-dependent bytes: leaf keys + bookmarks; a coarser level reads
     // the finer keys and bookmarks and writes keys, bookmarks, first children,
     // masks and the finer level's parents; the occupancy pass reads bookmarks.
     P.finish([&](const Prof::Rec& r) -> double {
-      if (r.set == kListSet) {  // a fill: its entries, and the parent level's E2 list read
-        const ListBufs& LB = impl->lists[r.level];
-        const double e2up = r.level - 1 >= 2 ? (double)impl->lists[r.level - 1].total[0] : 0.0;
-        return 4.0 * (double)(LB.total[0] + LB.total[1]) + 4.0 * e2up;
+      if (r.set == kListSet) {
+        const uint32_t l = (uint32_t)r.level;
+        const double nr = nb[rs][l];
+        if (r.cls == K_SCAN) return nr * 16 + 8;  // two counts in, two offsets out
+        // receiver key + parent in, two counts out; the parent lists and the
+        // parent-level source keys, masks and first children read once
+        const double side = (double)nb[rs][l - 1] * (ksz + 1 + 4 + 8) +
+                            (double)nb[0][l - 1] * (ksz + 1 + 4);
+        if (r.cls == K_COUNT) return side + nr * 8;
+        // a fill: also its entries and the parent level's E2 list read, and
+        // below D the next level's counts (masks and first children in, two
+        // counts out)
+        const ListBufs& LB = impl->lists[l];
+        const double e2up = l - 1 >= 2 ? (double)impl->lists[l - 1].total[0] : 0.0;
+        const double next_b =
+            l < D ? nr * 5 + (double)nb[0][l] + (double)nb[rs][l + 1] * 8 : 0.0;
+        return side + nr * 8 + next_b + 4.0 * (double)(LB.total[0] + LB.total[1]) + 4.0 * e2up;
       }
       if (r.set < 0) return 0.0;
       const uint32_t* c = nb[r.set == 0 ? 0 : rs];
