@@ -391,12 +391,13 @@ void fmmds_cache_info(uint64_t* hits, uint64_t* misses, uint64_t* miss_bytes,
 
 /*
  * Diagnostics: per-kernel timing. While enabled, every kernel a build
- * launches is bracketed by HIP events on the build stream; at the end of each
- * build the durations are added, per kernel, to process-wide totals together
- * with the algorithmic bytes of each launch (the reads and writes the method
- * itself needs, independent of caching). Enabling adds one stream
- * synchronization at the end of each build. Not thread-safe against
- * concurrent builds.
+ * launches is bracketed by HIP events on the stream it runs on; the
+ * durations are added, per kernel, to process-wide totals together with the
+ * algorithmic bytes of each launch (the reads and writes the method itself
+ * needs, independent of caching). A build does not wait for its timings:
+ * they are added once its launches have completed, at the latest when
+ * fmmds_profile_read or fmmds_profile_reset is called (both wait for the
+ * timed launches still pending). Not thread-safe against concurrent builds.
  */
 typedef struct fmmds_kernel_stat {
   char name[32];     /* kernel name, e.g. "sort_pass", "list_fill" */

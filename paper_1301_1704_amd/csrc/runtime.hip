@@ -358,6 +358,42 @@ std::mutex g_prof_mu;
 ClassStat g_prof[K_NCLASS];
 std::vector<hipEvent_t> g_events;  // reusable, guarded by g_prof_mu
 
+// Timed launches whose events may still be pending (guarded by g_prof_mu):
+// a build hands its records over without waiting for its stream, so that
+// profiling does not stall back-to-back builds.
+struct PendingRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+std::vector<PendingRec> g_pending;
+
+// Adds the launches whose end event has completed (every one, waiting for
+// it, with wait = true) to the per-class totals. Call with g_prof_mu held.
+void resolve_pending(bool wait) {
+  size_t keep = 0;
+  for (size_t i = 0; i < g_pending.size(); ++i) {
+    const PendingRec r = g_pending[i];
+    const hipError_t q = wait ? hipEventSynchronize(r.b) : hipEventQuery(r.b);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();
+      g_pending[keep++] = r;
+      continue;
+    }
+    float ms = 0;
+    if (q != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 0;
+    }
+    g_prof[r.cls].launches += 1;
+    g_prof[r.cls].ms += ms;
+    g_prof[r.cls].bytes += r.bytes;
+    g_events.push_back(r.a);
+    g_events.push_back(r.b);
+  }
+  g_pending.resize(keep);
+}
+
 constexpr int kListSet = 2;  // Prof record tag: a list kernel (count, scan, fill) of `level`
 
 struct Prof {
@@ -399,22 +435,16 @@ struct Prof {
     ck(hipEventRecord(b, s));
     recs.push_back({cls, a, b, bytes, set, level});
   }
-  // `extra(rec)` adds bytes known only after the launch (box counts).
+  // `extra(rec)` adds bytes known only after the launch (box counts). The
+  // durations are read once the launches have completed (resolve_pending),
+  // not by waiting here.
   template <typename X>
   void finish(X&& extra) {
     if (!on) return;
-    ck(hipStreamSynchronize(s));
     std::lock_guard<std::mutex> g(g_prof_mu);
-    for (Rec& r : recs) {
-      float ms = 0;
-      ck(hipEventElapsedTime(&ms, r.a, r.b));
-      g_prof[r.cls].launches += 1;
-      g_prof[r.cls].ms += ms;
-      g_prof[r.cls].bytes += r.bytes + extra(r);
-      g_events.push_back(r.a);
-      g_events.push_back(r.b);
-    }
+    for (Rec& r : recs) g_pending.push_back({r.cls, r.a, r.b, r.bytes + extra(r)});
     recs.clear();
+    resolve_pending(false);
   }
   void drop() {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -2125,11 +2155,13 @@ void fmmds_profile_enable(int on, const char* only) {
 
 void fmmds_profile_reset(void) {
   std::lock_guard<std::mutex> g(fmmds::g_prof_mu);
+  fmmds::resolve_pending(true);
   for (auto& c : fmmds::g_prof) c = fmmds::ClassStat();
 }
 
 uint32_t fmmds_profile_read(fmmds_kernel_stat* out, uint32_t cap) {
   std::lock_guard<std::mutex> g(fmmds::g_prof_mu);
+  fmmds::resolve_pending(true);
   uint32_t n = 0;
   for (int k = 0; k < fmmds::K_NCLASS; ++k) {
     if (fmmds::g_prof[k].launches == 0) continue;
