@@ -221,6 +221,26 @@ def test_range_error(F, bad):
     t.free()
 
 
+@pytest.mark.parametrize("cluster_s,which", [(0, "src"), (0, "recv"), (16, "src"), (16, "recv")])
+def test_range_error_both_paths(F, cluster_s, which):
+    """The range flag is reported whether the build reads it right after the
+    tables (with the depth rule, which needs the occupancies there) or only
+    at the finest level's list totals (without it), for a bad source point
+    or a bad receiver point; a build afterwards is unaffected."""
+    import torch
+    src = I.uniform_points(73, 6000)
+    recv = I.uniform_points(74, 5000)
+    (src if which == "src" else recv)[1234, 2] = 1.5
+    with pytest.raises(F.FmmdsError) as e:
+        F.build(parity.to_gpu(src), parity.to_gpu(recv), max_level=6, cluster_s=cluster_s)
+    assert e.value.status == F.ERR_RANGE
+    t = F.build(parity.to_gpu(I.uniform_points(75, 3000)), None, max_level=5,
+                cluster_s=cluster_s)
+    torch.cuda.synchronize()
+    assert t.n_boxes(0, 0) == 1
+    t.free()
+
+
 def test_list_level_errors(F):
     t = F.build(parity.to_gpu(I.uniform_points(81, 1000)), None, max_level=4)
     for bad in (0, 1, 5, 30):
