@@ -118,16 +118,19 @@ typedef struct fmmds_tree {
  *             sources and n_recv is ignored.
  *   opt:      host, required.
  *   out:      host; receives a tree owned by the library.
- * Synchronous: when it returns FMMDS_OK every output is complete and visible
- * to work later enqueued on opt->stream. Inputs are not retained. With
+ * Returns once the remaining work is enqueued on opt->stream: every output is
+ * complete and visible to work later enqueued there (or once the stream is
+ * synchronized), and every read of the inputs has completed, so they may be
+ * reused or freed at once. Inputs are not retained. With
  * separate receivers, the receivers' sort and tables run on a library-owned
  * stream of the current device (default priority, created on first use and
  * kept until the process ends) and are joined to opt->stream before the
  * lists. Concurrent calls on one device share that stream: their receiver
  * chains run one after another there, each still ordered after its own
  * caller's stream, so results are unaffected. The call waits on the host for
- * box counts and list sizes, so it cannot be captured into a graph (the
- * batched form can).
+ * the finest level's list sizes (with cluster_s > 0 also for the box counts
+ * and occupancies after the tables, which set the depth), so it cannot be
+ * captured into a graph (the batched form can).
  */
 fmmds_status fmmds_build(const float* src_xyz, uint32_t n_src, const float* recv_xyz,
                          uint32_t n_recv, const fmmds_options* opt, fmmds_tree** out);
